@@ -1,0 +1,137 @@
+/* sdl.h -- C ABI of the MI355X (gfx950) separable dictionary learning library.
+ *
+ * Method: C. Rusu, P. Irofti, "Efficient and Parallel Separable Dictionary
+ * Learning" (arXiv:2007.03800).  N two-dimensional signals Y_k (m1 x m2) are
+ * approximated as Y_k ~ D1 X_k D2^T with s-sparse X_k (n1 x n2) and unit-norm
+ * atoms (eq. (1)).  Sparse coding is 2D-OMP (Sec. III, step 1); the dictionary
+ * updates are the least-squares solutions of Corollary 1 (D1) and
+ * Proposition 1 (D2) followed by normalisation; learning iterates them as in
+ * Algorithm 1.
+ *
+ * Layout: every matrix is column-major (the paper's vec, Sec. I).
+ *   signal k, pixel (i,j):  Y[k*m1*m2 + i + j*m1]
+ *   D1 (m1 x n1): D1[p + i*m1];  D2 (m2 x n2): D2[q + j*m2]; always FP64 (master copy)
+ *   atom index a = i + n1*j, the column of D2 (x) D1 that multiplies vec X_k
+ *   supp[k*s + t]: t-th atom chosen for signal k (selection order), -1 = unused slot
+ *   coef[k*s + t]: its coefficient, 0 in unused slots
+ * Element type of Y, coef and res2: double for SDL_FP64, float for SDL_FP32.
+ *
+ * Pointers: every array pointer is a DEVICE pointer (HIP global memory) unless
+ * marked "host".  The caller allocates and owns all of them and keeps them alive
+ * until the work queued on `stream` has completed.  The library owns only its
+ * internal workspace (allocated on first use per device and stream, grown on
+ * demand, released at process exit).  Calls that share a stream are ordered;
+ * calls on different streams must not share output buffers.
+ *
+ * Errors: nothing is thrown across this ABI.  Arguments are validated before any
+ * work is queued; a negative status is returned and sdl_last_error() gives a
+ * thread-local message.  SDL_E_SINGULAR (a dictionary update whose Gram sum is
+ * not positive definite) leaves that dictionary unchanged and is reported after
+ * the remaining work has run.
+ */
+#ifndef SDL_H
+#define SDL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDL_ABI_VERSION 1
+
+typedef enum { SDL_FP64 = 0, SDL_FP32 = 1 } sdl_prec;
+
+enum {
+  SDL_OK = 0,
+  SDL_E_INVAL = -1,       /* null pointer, bad enum, negative count */
+  SDL_E_SHAPE = -2,       /* s > n1*n2, s > m1*m2, non-positive or too large sizes */
+  SDL_E_DEVICE = -3,      /* a HIP call failed (message holds hipGetErrorString) */
+  SDL_E_NOMEM = -4,       /* workspace allocation failed */
+  SDL_E_SINGULAR = -5,    /* update Gram sum not positive definite; dictionary kept */
+  SDL_E_NONFINITE = -6,   /* check_finite found NaN/Inf in Y or a dictionary */
+  SDL_E_UNSUPPORTED = -7  /* valid but not supported by this build (see message) */
+};
+
+/* Limits of this build (per problem). */
+#define SDL_MAX_M 64      /* m1, m2 */
+#define SDL_MAX_N 64      /* n1, n2 */
+#define SDL_MAX_S 32      /* s */
+
+/* One dictionary problem; an array of them is one (possibly uneven) batch. */
+typedef struct sdl_problem {
+  int32_t m1, m2, n1, n2, s;
+  int32_t reserved;       /* must be 0 */
+  int64_t N;              /* number of signals, >= 0 */
+  const void* Y;          /* N*m1*m2 elements */
+  double* D1;             /* m1*n1, unit-norm columns; input (sparse_code), in/out (update, learn) */
+  double* D2;             /* m2*n2 */
+  int32_t* supp;          /* N*s, output (sparse_code, learn), input (tmod_update) */
+  void* coef;             /* N*s, output; rescaled in place by tmod_update */
+  void* res2;             /* N, ||Y_k - D1 X_k D2^T||_F^2, output; may be NULL */
+} sdl_problem;
+
+/* Counters and timings filled when sdl_options.stats is set (host memory). */
+typedef struct sdl_stats {
+  int64_t early_stops;      /* signals that ended with fewer than s atoms */
+  int64_t fp64_pivots;      /* FP32 path: Cholesky rows recomputed in FP64 (small pivot) */
+  int64_t unused_atoms;     /* atoms kept unchanged because no code used them */
+  int64_t singular_updates; /* dictionary updates skipped as not positive definite */
+  /* Per-kernel device time when sdl_options.timing = 1, measured with HIP events on
+   * the call's stream.  Index: 0 sparse coding, 1 TMOD sums, 2 partial reduction,
+   * 3 solve+normalise, 4 dictionary prep, 5 RMSE, 6 code rescale. */
+  double kernel_ms[8];
+  int64_t kernel_launches[8];
+} sdl_stats;
+
+typedef struct sdl_options {
+  int32_t prec;             /* sdl_prec, default SDL_FP64 */
+  int32_t schedule;         /* sdl_learn: 0 = Algorithm 1 (OMP, D1, OMP, D2), 1 = (OMP, D2, D1) */
+  int32_t use_graph;        /* sdl_learn: replay one iteration as a HIP graph (default 1) */
+  int32_t check_finite;     /* scan Y and dictionaries for NaN/Inf first (default 0) */
+  int32_t timing;           /* fill stats->kernel_ms (eager launches with events; default 0) */
+  int32_t kernel;           /* sparse-coding kernel: 0 auto, 1 generic, 2 register-resident fast path */
+  double stop_rel;          /* OMP stops when max |corr| <= stop_rel*||Y_k||_F; default 1e-14 (FP64), 1e-6 (FP32) */
+  double dep_eps;           /* OMP stops when the new Gram pivot <= dep_eps*G_aa; default 1e-10 */
+  double pivot_fp64;        /* FP32: pivots below pivot_fp64*G_aa are recomputed in FP64; default 1e-3 */
+  sdl_stats* stats;         /* host, optional */
+} sdl_options;
+
+/* Fill *o with the defaults above (prec = SDL_FP64).  Passing NULL options to the
+ * calls below means these defaults. */
+void sdl_default_options(sdl_options* o);
+
+/* 2D-OMP sparse coding (Sec. III step 1; 2D-OMP equals OMP on D2 (x) D1, Sec. II):
+ * for every signal, s greedy steps choose the atom whose correlation with the
+ * residual is largest in magnitude (ties: smallest a), then re-fit all chosen
+ * coefficients by least squares.  Writes supp, coef, res2.  Asynchronous on
+ * `stream` (a hipStream_t; NULL = default stream). */
+int sdl_sparse_code(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream);
+
+/* TMOD dictionary update(s) from the codes in supp/coef (Algorithm 1 steps 2 and
+ * 4; Corollary 1 for D1, Proposition 1 for D2).  sides: 1 = D1, 2 = D2, 3 = D1
+ * then D2.  For each side: partial sums over all signals, FP64 solve on the
+ * atoms used by some code, unit-norm normalisation, and rescaling of coef so
+ * every product D1 X_k D2^T is unchanged.  Synchronises `stream` before
+ * returning the status. */
+int sdl_tmod_update(sdl_problem* p, int32_t nprob, uint32_t sides, const sdl_options* o, void* stream);
+
+/* Algorithm 1: K iterations of (2D-OMP, D1 update, 2D-OMP, D2 update), then a
+ * final 2D-OMP whose codes are returned in supp/coef/res2.  rmse_trace (host,
+ * nprob*(K+1) doubles, may be NULL): for problem q, entry q*(K+1)+t is
+ * sqrt(sum_k res2_k / (N*m1*m2)) of the 2D-OMP at the start of iteration t
+ * (t = K: the final one).  D1, D2 are updated in place.  Synchronises. */
+int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, const sdl_options* o,
+              void* stream);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* sdl_last_error(void);
+
+/* SDL_ABI_VERSION of the built library. */
+int sdl_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDL_H */

@@ -1,0 +1,92 @@
+"""ctypes view of include/sdl.h (argument marshalling only; all work runs in libsdl.so)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsdl.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "sdl.h")
+
+SDL_FP64, SDL_FP32 = 0, 1
+STATUS = {0: "SDL_OK", -1: "SDL_E_INVAL", -2: "SDL_E_SHAPE", -3: "SDL_E_DEVICE", -4: "SDL_E_NOMEM",
+          -5: "SDL_E_SINGULAR", -6: "SDL_E_NONFINITE", -7: "SDL_E_UNSUPPORTED"}
+KERNEL_CLASSES = ["sparse_code", "tmod_sums", "reduce", "solve", "prep", "rmse", "rescale", "spare"]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m1", ctypes.c_int32), ("m2", ctypes.c_int32), ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+                ("s", ctypes.c_int32), ("reserved", ctypes.c_int32), ("N", ctypes.c_int64),
+                ("Y", ctypes.c_void_p), ("D1", ctypes.c_void_p), ("D2", ctypes.c_void_p),
+                ("supp", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("res2", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("early_stops", ctypes.c_int64), ("fp64_pivots", ctypes.c_int64), ("unused_atoms", ctypes.c_int64),
+                ("singular_updates", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 8),
+                ("kernel_launches", ctypes.c_int64 * 8)]
+
+    def as_dict(self):
+        return dict(early_stops=self.early_stops, fp64_pivots=self.fp64_pivots, unused_atoms=self.unused_atoms,
+                    singular_updates=self.singular_updates,
+                    kernel_ms={KERNEL_CLASSES[i]: self.kernel_ms[i] for i in range(8) if self.kernel_launches[i]},
+                    kernel_launches={KERNEL_CLASSES[i]: self.kernel_launches[i] for i in range(8)
+                                     if self.kernel_launches[i]})
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("schedule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("check_finite", ctypes.c_int32), ("timing", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("stop_rel", ctypes.c_double), ("dep_eps", ctypes.c_double), ("pivot_fp64", ctypes.c_double),
+                ("stats", ctypes.POINTER(Stats))]
+
+
+class SdlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libsdl.so; raises if the HIP library has not been built (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsdl.so is not built; run `python -m paper_2007_03800_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(Problem)
+        L.sdl_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.sdl_default_options.restype = None
+        L.sdl_sparse_code.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p]
+        L.sdl_tmod_update.argtypes = [P, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(Options), ctypes.c_void_p]
+        L.sdl_learn.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(Options),
+                                ctypes.c_void_p]
+        for f in (L.sdl_sparse_code, L.sdl_tmod_update, L.sdl_learn):
+            f.restype = ctypes.c_int
+        L.sdl_last_error.restype = ctypes.c_char_p
+        L.sdl_last_error.argtypes = []
+        L.sdl_abi_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != 0:
+        raise SdlError(status, lib().sdl_last_error().decode())
+
+
+def default_options() -> Options:
+    o = Options()
+    lib().sdl_default_options(ctypes.byref(o))
+    return o
+
+
+def header_functions():
+    """Names of the functions include/sdl.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdl_[a-z0-9_]+)\s*\(", txt)))

@@ -1,0 +1,141 @@
+"""Python binding of the C ABI (include/sdl.h) over torch device tensors.
+
+torch provides device memory and the HIP stream; every step of the method runs
+in libsdl.so.  Tensors are kept in the ABI's memory layout (column-major
+matrices), so no data is reshaped on the way in:
+
+    Y     (N, m2, m1)  signal k, pixel (i, j) at Y[k, j, i]
+    D1    (n1, m1)     float64, atom i at D1[i, :]      (memory of the m1 x n1 column-major matrix)
+    D2    (n2, m2)     float64
+    supp  (N, s) int32, coef (N, s), res2 (N,)  (dtype of Y)
+
+``Problem.from_math`` converts math-shaped inputs once.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from . import _native
+
+_DT = {torch.float64: _native.SDL_FP64, torch.float32: _native.SDL_FP32}
+
+
+class Problem:
+    """One dictionary problem's device buffers, in ABI layout."""
+
+    def __init__(self, Y: torch.Tensor, D1: torch.Tensor, D2: torch.Tensor, s: int,
+                 supp: torch.Tensor | None = None, coef: torch.Tensor | None = None,
+                 res2: torch.Tensor | None = None, with_res2: bool = True):
+        if Y.dim() != 3 or D1.dim() != 2 or D2.dim() != 2:
+            raise ValueError("Y must be (N, m2, m1), D1 (n1, m1), D2 (n2, m2)")
+        self.N, self.m2, self.m1 = Y.shape
+        self.n1, self.n2 = D1.shape[0], D2.shape[0]
+        if D1.shape[1] != self.m1 or D2.shape[1] != self.m2:
+            raise ValueError("dictionary row counts do not match the signal shape")
+        if Y.dtype not in _DT:
+            raise ValueError("Y must be float32 or float64")
+        for t in (Y, D1, D2):
+            if not t.is_contiguous():
+                raise ValueError("tensors must be contiguous (ABI layout)")
+        if D1.dtype != torch.float64 or D2.dtype != torch.float64:
+            raise ValueError("dictionaries are FP64 master copies")
+        self.s = int(s)
+        dev = Y.device
+        self.Y, self.D1, self.D2 = Y, D1, D2
+        self.supp = supp if supp is not None else torch.empty((self.N, self.s), dtype=torch.int32, device=dev)
+        self.coef = coef if coef is not None else torch.empty((self.N, self.s), dtype=Y.dtype, device=dev)
+        self.res2 = res2 if res2 is not None else (
+            torch.empty(self.N, dtype=Y.dtype, device=dev) if with_res2 else None)
+
+    @classmethod
+    def from_math(cls, Y, D1, D2, s, dtype=torch.float32, device="cuda"):
+        """Y (N, m1, m2), D1 (m1, n1), D2 (m2, n2) (numpy or torch) -> ABI-layout device buffers."""
+        Y = torch.as_tensor(Y)
+        D1 = torch.as_tensor(D1)
+        D2 = torch.as_tensor(D2)
+        Yc = Y.to(device=device, dtype=dtype).transpose(1, 2).contiguous()
+        return cls(Yc, D1.to(device=device, dtype=torch.float64).t().contiguous(),
+                   D2.to(device=device, dtype=torch.float64).t().contiguous(), s)
+
+    @property
+    def prec(self):
+        return _DT[self.Y.dtype]
+
+    def d1(self):
+        """D1 in math shape (m1, n1), on the host."""
+        return self.D1.t().cpu().numpy()
+
+    def d2(self):
+        return self.D2.t().cpu().numpy()
+
+    def struct(self) -> _native.Problem:
+        def p(t):
+            return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        return _native.Problem(self.m1, self.m2, self.n1, self.n2, self.s, 0, self.N, p(self.Y), p(self.D1),
+                               p(self.D2), p(self.supp), p(self.coef), p(self.res2))
+
+
+def _options(problems, stats=None, **kw):
+    o = _native.default_options()
+    precs = {pr.prec for pr in problems}
+    if len(precs) > 1:
+        raise ValueError("all problems of one call share a precision")
+    o.prec = precs.pop() if precs else _native.SDL_FP64
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, v)
+    if stats is not None:
+        o.stats = ctypes.pointer(stats)
+    return o
+
+
+def _array(problems):
+    arr = (_native.Problem * max(1, len(problems)))()
+    for i, pr in enumerate(problems):
+        arr[i] = pr.struct()
+    return arr
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def sparse_code(problems: Problem | Sequence[Problem], stream=None, stats=None, **opts):
+    """2D-OMP of every signal of every problem (asynchronous on the stream)."""
+    problems = [problems] if isinstance(problems, Problem) else list(problems)
+    o = _options(problems, stats, **opts)
+    arr = _array(problems)
+    _native.check(_native.lib().sdl_sparse_code(arr, len(problems), ctypes.byref(o), _stream(stream)))
+    return problems
+
+
+def tmod_update(problems: Problem | Sequence[Problem], sides: int = 3, stream=None, stats=None, **opts):
+    """Dictionary update(s) from the current codes; rescales coef in place.  Synchronises."""
+    problems = [problems] if isinstance(problems, Problem) else list(problems)
+    o = _options(problems, stats, **opts)
+    arr = _array(problems)
+    _native.check(_native.lib().sdl_tmod_update(arr, len(problems), sides, ctypes.byref(o), _stream(stream)))
+    return problems
+
+
+def learn(problems: Problem | Sequence[Problem], K: int, stream=None, stats=None, **opts):
+    """Algorithm 1 for K iterations plus a final 2D-OMP.  Returns the RMSE trace (nprob, K+1)."""
+    import numpy as np
+    problems = [problems] if isinstance(problems, Problem) else list(problems)
+    o = _options(problems, stats, **opts)
+    arr = _array(problems)
+    trace = np.zeros((max(1, len(problems)), K + 1), dtype=np.float64)
+    st = _native.lib().sdl_learn(arr, len(problems), K, trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o),
+                                 _stream(stream))
+    _native.check(st)
+    return trace[:len(problems)]
+
+
+def new_stats() -> _native.Stats:
+    return _native.Stats()

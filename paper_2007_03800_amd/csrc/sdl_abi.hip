@@ -1,0 +1,555 @@
+// Host side of the C ABI declared in include/sdl.h: argument validation,
+// workspace, launch sequencing (Algorithm 1), HIP graph replay and timing.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sdl_internal.h"
+
+using namespace sdl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(SDL_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------ per-stream context
+
+struct Ctx {
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t side = nullptr;  // internal stream for graph replay (default priority)
+  std::vector<hipEvent_t> ev;  // timing events
+  hipEvent_t join_a = nullptr, join_b = nullptr;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Ctx*> g_ctx;
+
+int get_ctx(hipStream_t st, Ctx** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, st);
+  auto it = g_ctx.find(key);
+  if (it == g_ctx.end()) {
+    Ctx* c = new Ctx();
+    c->device = dev;
+    hipError_t e = omp_generic_init_device();
+    if (e != hipSuccess) {
+      delete c;
+      return fail(SDL_E_DEVICE, "kernel attribute setup: %s", hipGetErrorString(e));
+    }
+    it = g_ctx.emplace(key, c).first;
+  }
+  *out = it->second;
+  return SDL_OK;
+}
+
+int ensure_ws(Ctx* c, size_t bytes, hipStream_t st) {
+  if (c->ws_bytes >= bytes) return SDL_OK;
+  if (c->ws) {
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  size_t n = bytes + bytes / 4 + 4096;
+  if (hipMalloc(&c->ws, n) != hipSuccess) {
+    c->ws = nullptr;
+    return fail(SDL_E_NOMEM, "workspace allocation of %zu bytes failed", n);
+  }
+  c->ws_bytes = n;
+  return SDL_OK;
+}
+
+// bump allocator over the workspace
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------ options / validation
+
+struct Opt {
+  int prec, schedule, use_graph, check_finite, timing, kernel;
+  double stop_rel, dep_eps, pivot_fp64;
+  sdl_stats* stats;
+};
+
+Opt resolve(const sdl_options* o) {
+  sdl_options d;
+  sdl_default_options(&d);
+  if (!o) o = &d;
+  Opt r;
+  r.prec = o->prec;
+  r.schedule = o->schedule;
+  r.use_graph = o->use_graph;
+  r.check_finite = o->check_finite;
+  r.timing = o->timing;
+  r.kernel = o->kernel;
+  r.stop_rel = o->stop_rel >= 0 ? o->stop_rel : (o->prec == SDL_FP64 ? 1e-14 : 1e-6);
+  r.dep_eps = o->dep_eps >= 0 ? o->dep_eps : 1e-10;
+  r.pivot_fp64 = o->pivot_fp64 >= 0 ? o->pivot_fp64 : 1e-3;
+  r.stats = o->stats;
+  return r;
+}
+
+int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_in) {
+  if (nprob < 0) return fail(SDL_E_INVAL, "nprob = %d < 0", nprob);
+  if (nprob > 0 && !p) return fail(SDL_E_INVAL, "problem array is NULL");
+  if (o.prec != SDL_FP64 && o.prec != SDL_FP32) return fail(SDL_E_INVAL, "prec = %d is not an sdl_prec", o.prec);
+  if (o.schedule != 0 && o.schedule != 1) return fail(SDL_E_INVAL, "schedule = %d (0 or 1)", o.schedule);
+  if (o.kernel < 0 || o.kernel > 2) return fail(SDL_E_INVAL, "kernel = %d (0, 1 or 2)", o.kernel);
+  const size_t elem = o.prec == SDL_FP64 ? 8 : 4;
+  for (int q = 0; q < nprob; ++q) {
+    const sdl_problem& r = p[q];
+    if (r.m1 <= 0 || r.m2 <= 0 || r.n1 <= 0 || r.n2 <= 0 || r.s <= 0)
+      return fail(SDL_E_SHAPE, "problem %d: sizes must be positive (m1=%d m2=%d n1=%d n2=%d s=%d)", q, r.m1, r.m2,
+                  r.n1, r.n2, r.s);
+    if (r.N < 0) return fail(SDL_E_INVAL, "problem %d: N = %lld < 0", q, (long long)r.N);
+    if (r.reserved != 0) return fail(SDL_E_INVAL, "problem %d: reserved field must be 0", q);
+    if ((int64_t)r.s > (int64_t)r.n1 * r.n2 || (int64_t)r.s > (int64_t)r.m1 * r.m2)
+      return fail(SDL_E_SHAPE, "problem %d: s = %d exceeds n1*n2 = %d or m1*m2 = %d", q, r.s, r.n1 * r.n2,
+                  r.m1 * r.m2);
+    if (r.m1 > SDL_MAX_M || r.m2 > SDL_MAX_M || r.n1 > SDL_MAX_N || r.n2 > SDL_MAX_N || r.s > SDL_MAX_S)
+      return fail(SDL_E_SHAPE, "problem %d: sizes exceed the limits m <= %d, n <= %d, s <= %d", q, SDL_MAX_M,
+                  SDL_MAX_N, SDL_MAX_S);
+    if (!r.D1 || !r.D2) return fail(SDL_E_INVAL, "problem %d: D1/D2 is NULL", q);
+    if (r.N > 0 && (!r.Y || !r.supp || !r.coef)) return fail(SDL_E_INVAL, "problem %d: Y/supp/coef is NULL", q);
+    (void)need_codes_in;
+    if (omp_generic_lds_bytes(r.m1, r.m2, r.n1, r.n2, r.s, elem) > 160 * 1024)
+      return fail(SDL_E_UNSUPPORTED, "problem %d: working set of one signal exceeds the 160 KiB LDS", q);
+  }
+  return SDL_OK;
+}
+
+// ------------------------------------------------------------------ per-problem buffers
+
+struct PBuf {
+  void* Dc1;  // compute-type copies
+  void* Dc2;
+  double* G1_64;
+  double* G2_64;
+  void* G1c;
+  void* G2c;
+  double* part;
+  double* sums;
+  double* w;
+  double* rpart;
+  int nblk, rblk, nent;
+};
+
+struct Plan {
+  std::vector<PBuf> pb;
+  int* status;
+  unsigned long long* counters;
+  int* iter;     // per-problem RMSE counters
+  double* trace; // device trace
+  size_t bytes;
+};
+
+// Lay out the workspace; with base == nullptr only measures.
+void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Plan* pl) {
+  Bump b(base);
+  pl->pb.resize(nprob);
+  pl->status = b.take<int>(4);
+  pl->counters = b.take<unsigned long long>(kNumCounters);
+  pl->iter = b.take<int>(nprob > 0 ? nprob : 1);
+  pl->trace = b.take<double>((size_t)(nprob > 0 ? nprob : 1) * (K + 1));
+  for (int q = 0; q < nprob; ++q) {
+    const sdl_problem& r = p[q];
+    PBuf& x = pl->pb[q];
+    x.Dc1 = b.take<char>(elem * r.m1 * r.n1);
+    x.Dc2 = b.take<char>(elem * r.m2 * r.n2);
+    x.G1_64 = b.take<double>((size_t)r.n1 * r.n1);
+    x.G2_64 = b.take<double>((size_t)r.n2 * r.n2);
+    x.G1c = b.take<char>(elem * r.n1 * r.n1);
+    x.G2c = b.take<char>(elem * r.n2 * r.n2);
+    const int na = r.n1 > r.n2 ? r.n1 : r.n2, mr = r.m1 > r.m2 ? r.m1 : r.m2;
+    x.nent = na * na + mr * na;
+    x.nblk = tmod_num_blocks(r.N);
+    x.rblk = rmse_num_blocks(r.N);
+    x.part = b.take<double>((size_t)x.nblk * x.nent);
+    x.sums = b.take<double>((size_t)x.nent);
+    x.w = b.take<double>((size_t)na);
+    x.rpart = b.take<double>((size_t)x.rblk);
+  }
+  pl->bytes = b.off + 256;
+}
+
+// ------------------------------------------------------------------ launch helpers
+
+struct Launcher {
+  hipStream_t st;
+  bool timing;
+  Ctx* ctx;
+  std::vector<std::pair<int, int>>* marks;  // (class, event index of start)
+  int next_ev = 0;
+
+  int begin(int cls) {
+    if (!timing) return SDL_OK;
+    if ((size_t)next_ev + 2 > ctx->ev.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ctx->ev.push_back(e);
+      }
+    }
+    HIP_TRY(hipEventRecord(ctx->ev[next_ev], st));
+    marks->push_back({cls, next_ev});
+    next_ev += 2;
+    return SDL_OK;
+  }
+  int end() {
+    if (!timing) return SDL_OK;
+    HIP_TRY(hipEventRecord(ctx->ev[marks->back().second + 1], st));
+    return SDL_OK;
+  }
+};
+
+#define SDL_TRY(expr)            \
+  do {                           \
+    int s_ = (expr);             \
+    if (s_ != SDL_OK) return s_; \
+  } while (0)
+
+template <typename T>
+OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl) {
+  OmpArgs<T> a;
+  a.m1 = r.m1; a.m2 = r.m2; a.n1 = r.n1; a.n2 = r.n2; a.s = r.s; a.N = r.N;
+  a.Y = (const T*)r.Y;
+  a.D1 = (const T*)b.Dc1;
+  a.D2 = (const T*)b.Dc2;
+  a.G1 = (const T*)b.G1c;
+  a.G2 = (const T*)b.G2c;
+  a.supp = r.supp;
+  a.coef = (T*)r.coef;
+  a.res2 = (T*)r.res2;
+  a.stop_rel = o.stop_rel;
+  a.dep_eps = o.dep_eps;
+  a.pivot_fp64 = o.pivot_fp64;
+  a.counters = pl.counters;
+  return a;
+}
+
+template <typename T>
+int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, T* res2_override, Launcher& L) {
+  OmpArgs<T> a = omp_args<T>(r, b, o, pl);
+  if (res2_override) a.res2 = res2_override;
+  const bool fast = o.kernel != 1 && omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s);
+  if (o.kernel == 2 && !fast)
+    return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for m=%dx%d n=%dx%d s=%d in this precision", r.m1,
+                r.m2, r.n1, r.n2, r.s);
+  SDL_TRY(L.begin(0));
+  HIP_TRY(fast ? launch_omp_fast<T>(a, L.st) : launch_omp_generic<T>(a, L.st));
+  return L.end();
+}
+
+template <typename T>
+int run_prep(const sdl_problem& r, const PBuf& b, Launcher& L) {
+  SDL_TRY(L.begin(4));
+  HIP_TRY(launch_dict_prep<T>(r.D1, r.m1, r.n1, (T*)b.Dc1, b.G1_64, (T*)b.G1c, L.st));
+  HIP_TRY(launch_dict_prep<T>(r.D2, r.m2, r.n2, (T*)b.Dc2, b.G2_64, (T*)b.G2c, L.st));
+  return L.end();
+}
+
+// one TMOD half-step: sums -> reduce -> solve (+ optional rescale of coef)
+template <typename T>
+int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bool rescale, Launcher& L) {
+  TmodArgs<T> a;
+  a.side = side;
+  a.m1 = r.m1; a.m2 = r.m2; a.n1 = r.n1; a.n2 = r.n2; a.s = r.s; a.N = r.N;
+  a.Y = (const T*)r.Y;
+  a.Dother = (const T*)(side == 1 ? b.Dc2 : b.Dc1);
+  a.supp = r.supp;
+  a.coef = (const T*)r.coef;
+  const int na = side == 1 ? r.n1 : r.n2, mr = side == 1 ? r.m1 : r.m2;
+  const int nent = na * na + mr * na;
+  SDL_TRY(L.begin(1));
+  HIP_TRY(launch_tmod_sums<T>(a, b.part, b.nblk, L.st));
+  SDL_TRY(L.end());
+  SDL_TRY(L.begin(2));
+  HIP_TRY(launch_reduce_partials(b.part, b.nblk, nent, b.sums, L.st));
+  SDL_TRY(L.end());
+  SDL_TRY(L.begin(3));
+  if (side == 1)
+    HIP_TRY(launch_tmod_solve<T>(b.sums, r.m1, r.n1, r.D1, (T*)b.Dc1, b.G1_64, (T*)b.G1c, b.w, pl.status,
+                                 pl.counters, L.st));
+  else
+    HIP_TRY(launch_tmod_solve<T>(b.sums, r.m2, r.n2, r.D2, (T*)b.Dc2, b.G2_64, (T*)b.G2c, b.w, pl.status,
+                                 pl.counters, L.st));
+  SDL_TRY(L.end());
+  if (rescale) {
+    SDL_TRY(L.begin(6));
+    HIP_TRY(launch_rescale<T>(side, r.n1, r.s, r.N, r.supp, (T*)r.coef, b.w, L.st));
+    SDL_TRY(L.end());
+  }
+  return SDL_OK;
+}
+
+template <typename T>
+int run_rmse(const sdl_problem& r, const PBuf& b, const Plan& pl, int q, int K, Launcher& L) {
+  SDL_TRY(L.begin(5));
+  HIP_TRY(launch_rmse<T>((const T*)r.res2, r.N, (double)r.N * r.m1 * r.m2, b.rpart, b.rblk, pl.trace, 1,
+                         q * (K + 1), pl.iter + q, L.st));
+  return L.end();
+}
+
+int begin_call(hipStream_t st, Ctx* ctx, const Plan& pl, int nprob) {
+  (void)ctx;
+  HIP_TRY(launch_fill_int(pl.status, 4, 0, st));
+  HIP_TRY(launch_fill_int((int*)pl.counters, 2 * kNumCounters, 0, st));
+  HIP_TRY(launch_fill_int(pl.iter, nprob > 0 ? nprob : 1, 0, st));
+  return SDL_OK;
+}
+
+template <typename T>
+int run_check_finite(const sdl_problem* p, int nprob, const Plan& pl, hipStream_t st) {
+  for (int q = 0; q < nprob; ++q) {
+    HIP_TRY(launch_check_finite<T>((const T*)p[q].Y, p[q].N * p[q].m1 * p[q].m2, pl.status, st));
+    HIP_TRY(launch_check_finite<double>(p[q].D1, (int64_t)p[q].m1 * p[q].n1, pl.status, st));
+    HIP_TRY(launch_check_finite<double>(p[q].D2, (int64_t)p[q].m2 * p[q].n2, pl.status, st));
+  }
+  return SDL_OK;
+}
+
+// Sync, read back status / counters / timings.
+int finish_call(hipStream_t st, Ctx* ctx, const Plan& pl, const Opt& o, std::vector<std::pair<int, int>>& marks,
+                bool sync) {
+  if (!sync && !o.stats) return SDL_OK;
+  HIP_TRY(hipStreamSynchronize(st));
+  int status = 0;
+  unsigned long long ctr[kNumCounters];
+  HIP_TRY(hipMemcpy(&status, pl.status, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ctr, pl.counters, sizeof(ctr), hipMemcpyDeviceToHost));
+  if (o.stats) {
+    o.stats->early_stops += (int64_t)ctr[kCtrEarlyStop];
+    o.stats->fp64_pivots += (int64_t)ctr[kCtrFp64Pivot];
+    o.stats->unused_atoms += (int64_t)ctr[kCtrUnusedAtoms];
+    o.stats->singular_updates += (int64_t)ctr[kCtrSingular];
+    for (auto& m : marks) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[m.second], ctx->ev[m.second + 1]));
+      o.stats->kernel_ms[m.first] += ms;
+      o.stats->kernel_launches[m.first] += 1;
+    }
+  }
+  if (status & kStatusNonfinite) return fail(SDL_E_NONFINITE, "non-finite value in Y or a dictionary");
+  if (status & kStatusSingular)
+    return fail(SDL_E_SINGULAR, "a dictionary update's Gram sum was not positive definite; dictionary kept");
+  return SDL_OK;
+}
+
+template <typename T>
+int sparse_code_impl(const sdl_problem* p, int nprob, const Opt& o, hipStream_t st) {
+  Ctx* ctx;
+  SDL_TRY(get_ctx(st, &ctx));
+  Plan pl;
+  layout(p, nprob, sizeof(T), 0, nullptr, &pl);
+  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
+  layout(p, nprob, sizeof(T), 0, ctx->ws, &pl);
+  std::vector<std::pair<int, int>> marks;
+  Launcher L{st, o.timing != 0 && o.stats != nullptr, ctx, &marks};
+  SDL_TRY(begin_call(st, ctx, pl, nprob));
+  if (o.check_finite) {
+    SDL_TRY(run_check_finite<T>(p, nprob, pl, st));
+    SDL_TRY(finish_call(st, ctx, pl, o, marks, true));
+  }
+  for (int q = 0; q < nprob; ++q) {
+    if (p[q].N == 0) continue;
+    SDL_TRY(run_prep<T>(p[q], pl.pb[q], L));
+    SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, nullptr, L));
+  }
+  return finish_call(st, ctx, pl, o, marks, false);
+}
+
+template <typename T>
+int tmod_update_impl(sdl_problem* p, int nprob, uint32_t sides, const Opt& o, hipStream_t st) {
+  Ctx* ctx;
+  SDL_TRY(get_ctx(st, &ctx));
+  Plan pl;
+  layout(p, nprob, sizeof(T), 0, nullptr, &pl);
+  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
+  layout(p, nprob, sizeof(T), 0, ctx->ws, &pl);
+  std::vector<std::pair<int, int>> marks;
+  Launcher L{st, o.timing != 0 && o.stats != nullptr, ctx, &marks};
+  SDL_TRY(begin_call(st, ctx, pl, nprob));
+  if (o.check_finite) {
+    SDL_TRY(run_check_finite<T>(p, nprob, pl, st));
+    SDL_TRY(finish_call(st, ctx, pl, o, marks, true));
+  }
+  for (int q = 0; q < nprob; ++q) {
+    SDL_TRY(run_prep<T>(p[q], pl.pb[q], L));
+    if (sides & 1u) SDL_TRY(run_update<T>(1, p[q], pl.pb[q], pl, true, L));
+    if (sides & 2u) SDL_TRY(run_update<T>(2, p[q], pl.pb[q], pl, true, L));
+  }
+  return finish_call(st, ctx, pl, o, marks, true);
+}
+
+template <typename T>
+int one_iteration(sdl_problem* p, int nprob, int K, const Opt& o, const Plan& pl, Launcher& L) {
+  for (int q = 0; q < nprob; ++q) {
+    const sdl_problem& r = p[q];
+    if (r.N == 0) continue;
+    const PBuf& b = pl.pb[q];
+    SDL_TRY(run_omp<T>(r, b, o, pl, nullptr, L));
+    SDL_TRY(run_rmse<T>(r, b, pl, q, K, L));
+    if (o.schedule == 0) {
+      SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+      SDL_TRY(run_omp<T>(r, b, o, pl, nullptr, L));
+      SDL_TRY(run_update<T>(2, r, b, pl, false, L));
+    } else {
+      SDL_TRY(run_update<T>(2, r, b, pl, true, L));
+      SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+    }
+  }
+  return SDL_OK;
+}
+
+template <typename T>
+int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hipStream_t st) {
+  Ctx* ctx;
+  SDL_TRY(get_ctx(st, &ctx));
+  // res2 is needed for the RMSE trace; require it
+  for (int q = 0; q < nprob; ++q)
+    if (p[q].N > 0 && !p[q].res2) return fail(SDL_E_INVAL, "problem %d: sdl_learn needs res2", q);
+  Plan pl;
+  layout(p, nprob, sizeof(T), K, nullptr, &pl);
+  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
+  layout(p, nprob, sizeof(T), K, ctx->ws, &pl);
+  std::vector<std::pair<int, int>> marks;
+  const bool timing = o.timing != 0 && o.stats != nullptr;
+  Launcher L{st, timing, ctx, &marks};
+  SDL_TRY(begin_call(st, ctx, pl, nprob));
+  if (o.check_finite) {
+    SDL_TRY(run_check_finite<T>(p, nprob, pl, st));
+    SDL_TRY(finish_call(st, ctx, pl, o, marks, true));
+  }
+  for (int q = 0; q < nprob; ++q) SDL_TRY(run_prep<T>(p[q], pl.pb[q], L));
+  const bool graph = o.use_graph && !timing && K > 1;
+  if (graph) {
+    if (!ctx->side) {
+      HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&ctx->join_a, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&ctx->join_b, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(ctx->join_a, st));
+    HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->join_a, 0));
+    Launcher G{ctx->side, false, ctx, &marks};
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIP_TRY(hipStreamBeginCapture(ctx->side, hipStreamCaptureModeRelaxed));
+    int rc = one_iteration<T>(p, nprob, K, o, pl, G);
+    hipError_t ce = hipStreamEndCapture(ctx->side, &g);
+    if (rc != SDL_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    HIP_TRY(ce);
+    HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    for (int it = 0; it < K; ++it) HIP_TRY(hipGraphLaunch(ge, ctx->side));
+    HIP_TRY(hipEventRecord(ctx->join_b, ctx->side));
+    HIP_TRY(hipStreamWaitEvent(st, ctx->join_b, 0));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipGraphExecDestroy(ge));
+    HIP_TRY(hipGraphDestroy(g));
+  } else {
+    for (int it = 0; it < K; ++it) SDL_TRY(one_iteration<T>(p, nprob, K, o, pl, L));
+  }
+  for (int q = 0; q < nprob; ++q) {
+    if (p[q].N == 0) continue;
+    SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, nullptr, L));
+    SDL_TRY(run_rmse<T>(p[q], pl.pb[q], pl, q, K, L));
+  }
+  int rc = finish_call(st, ctx, pl, o, marks, true);
+  if (trace && (rc == SDL_OK || rc == SDL_E_SINGULAR)) {
+    std::vector<double> h((size_t)(nprob > 0 ? nprob : 1) * (K + 1), 0.0);
+    HIP_TRY(hipMemcpy(h.data(), pl.trace, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+    memcpy(trace, h.data(), sizeof(double) * (size_t)nprob * (K + 1));
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sdl_default_options(sdl_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->prec = SDL_FP64;
+  o->schedule = 0;
+  o->use_graph = 1;
+  o->check_finite = 0;
+  o->timing = 0;
+  o->kernel = 0;
+  o->stop_rel = -1.0;
+  o->dep_eps = -1.0;
+  o->pivot_fp64 = -1.0;
+  o->stats = nullptr;
+}
+
+int sdl_sparse_code(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  SDL_TRY(validate(p, nprob, opt, false));
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? sparse_code_impl<double>(p, nprob, opt, st) : sparse_code_impl<float>(p, nprob, opt, st);
+}
+
+int sdl_tmod_update(sdl_problem* p, int32_t nprob, uint32_t sides, const sdl_options* o, void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  SDL_TRY(validate(p, nprob, opt, true));
+  if (sides < 1 || sides > 3) return fail(SDL_E_INVAL, "sides = %u (1, 2 or 3)", sides);
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? tmod_update_impl<double>(p, nprob, sides, opt, st)
+                              : tmod_update_impl<float>(p, nprob, sides, opt, st);
+}
+
+int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, const sdl_options* o, void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  SDL_TRY(validate(p, nprob, opt, false));
+  if (K < 0) return fail(SDL_E_INVAL, "K = %d < 0", K);
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? learn_impl<double>(p, nprob, K, rmse_trace, opt, st)
+                              : learn_impl<float>(p, nprob, K, rmse_trace, opt, st);
+}
+
+const char* sdl_last_error(void) { return g_err.c_str(); }
+
+int sdl_abi_version(void) { return SDL_ABI_VERSION; }
+
+}  // extern "C"

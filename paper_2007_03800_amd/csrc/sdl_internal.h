@@ -1,0 +1,82 @@
+// Internal declarations shared by the HIP translation units of libsdl.
+// Device code targets gfx950 (CDNA4, wave64) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sdl.h"
+
+namespace sdl {
+
+constexpr int kWave = 64;
+
+// Device-side status bits, OR-ed into a per-call word and read back at sync.
+enum : int { kStatusSingular = 1, kStatusNonfinite = 2 };
+
+// Device counters (one int64-sized slot each) accumulated with integer atomics.
+enum : int { kCtrEarlyStop = 0, kCtrFp64Pivot = 1, kCtrUnusedAtoms = 2, kCtrSingular = 3, kNumCounters = 4 };
+
+// Arguments of one sparse-coding launch over one problem.
+template <typename T>
+struct OmpArgs {
+  int m1, m2, n1, n2, s;
+  int64_t N;
+  const T* Y;
+  const T* D1;  // m1 x n1 column-major, in the compute type
+  const T* D2;  // m2 x n2
+  const T* G1;  // n1 x n1 = D1^T D1
+  const T* G2;  // n2 x n2 = D2^T D2
+  int32_t* supp;
+  T* coef;
+  T* res2;  // may be null
+  double stop_rel, dep_eps, pivot_fp64;
+  unsigned long long* counters;  // kNumCounters entries
+};
+
+// Buffers describing one TMOD half-step for one problem.
+template <typename T>
+struct TmodArgs {
+  int side;  // 1: update D1 (Corollary 1), 2: update D2 (Proposition 1)
+  int m1, m2, n1, n2, s;
+  int64_t N;
+  const T* Y;
+  const T* Dother;  // compute-type copy of the dictionary that stays fixed
+  const int32_t* supp;
+  const T* coef;
+};
+
+// ---- launchers (defined in the .hip files) ----
+template <typename T>
+hipError_t launch_omp_generic(const OmpArgs<T>& a, hipStream_t st);
+template <typename T>
+bool omp_fast_supported(int m1, int m2, int n1, int n2, int s);
+template <typename T>
+hipError_t launch_omp_fast(const OmpArgs<T>& a, hipStream_t st);
+size_t omp_generic_lds_bytes(int m1, int m2, int n1, int n2, int s, size_t elem);
+hipError_t omp_generic_init_device();
+
+// Number of per-block partials used by the sums kernel for N signals (fixed function of N).
+int tmod_num_blocks(int64_t N);
+template <typename T>
+hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, int nblk, hipStream_t st);
+hipError_t launch_reduce_partials(const double* part, int nblk, int nent, double* out, hipStream_t st);
+// Solve + normalise. D: the dictionary being updated (mr x na FP64, in/out).
+// Writes D (unless singular), Dc (compute-type copy), G64, Gc, w; ORs status; counts unused atoms.
+template <typename T>
+hipError_t launch_tmod_solve(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc,
+                             double* w, int* status, unsigned long long* counters, hipStream_t st);
+template <typename T>
+hipError_t launch_dict_prep(const double* D, int mr, int na, T* Dc, double* G64, T* Gc, hipStream_t st);
+template <typename T>
+hipError_t launch_rescale(int side, int n1, int s, int64_t N, const int32_t* supp, T* coef, const double* w,
+                          hipStream_t st);
+int rmse_num_blocks(int64_t N);
+template <typename T>
+hipError_t launch_rmse(const T* res2, int64_t N, double denom, double* part, int nblk, double* trace,
+                       int stride, int offset, int* counter, hipStream_t st);
+template <typename T>
+hipError_t launch_check_finite(const T* x, int64_t n, int* status, hipStream_t st);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
+
+}  // namespace sdl

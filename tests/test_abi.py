@@ -1,0 +1,84 @@
+"""The C-ABI library loads, exports what include/sdl.h declares, and validates
+arguments before touching the device (these calls never reach a HIP call)."""
+import ctypes
+import subprocess
+
+import pytest
+
+from paper_2007_03800_amd import _native
+
+
+def test_header_symbols_exported():
+    names = _native.header_functions()
+    assert {"sdl_sparse_code", "sdl_tmod_update", "sdl_learn", "sdl_last_error", "sdl_default_options",
+            "sdl_abi_version"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", _native.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = _native.lib()
+    for n in names:
+        assert hasattr(lib, n)
+    assert lib.sdl_abi_version() == 1
+
+
+def _problem(**kw):
+    base = dict(m1=8, m2=8, n1=16, n2=16, s=8, reserved=0, N=10, Y=1, D1=2, D2=3, supp=4, coef=5, res2=6)
+    base.update(kw)
+    return _native.Problem(**base)
+
+
+def _call(fn, prob, opts=None, extra=()):
+    arr = (_native.Problem * 1)(prob)
+    o = opts if opts is not None else _native.default_options()
+    if fn == "sparse_code":
+        return _native.lib().sdl_sparse_code(arr, 1, ctypes.byref(o), None)
+    if fn == "tmod_update":
+        return _native.lib().sdl_tmod_update(arr, 1, extra[0] if extra else 3, ctypes.byref(o), None)
+    return _native.lib().sdl_learn(arr, 1, extra[0] if extra else 2, None, ctypes.byref(o), None)
+
+
+@pytest.mark.parametrize("fn", ["sparse_code", "tmod_update", "learn"])
+@pytest.mark.parametrize("kw,status", [
+    (dict(s=257), -2),           # s > n1*n2
+    (dict(m1=2, m2=2, s=5), -2),  # s > m1*m2
+    (dict(m1=0), -2),
+    (dict(n2=-3), -2),
+    (dict(s=0), -2),
+    (dict(N=-1), -1),
+    (dict(D1=None), -1),
+    (dict(Y=None), -1),
+    (dict(supp=None), -1),
+    (dict(coef=None), -1),
+    (dict(reserved=7), -1),
+    (dict(m1=65, n1=65), -2),
+    (dict(s=33, n1=16), -2),
+])
+def test_validation(fn, kw, status):
+    st = _call(fn, _problem(**kw))
+    assert st == status
+    assert _native.lib().sdl_last_error().decode() != ""
+
+
+def test_bad_enums():
+    o = _native.default_options()
+    o.prec = 5
+    assert _call("sparse_code", _problem(), o) == -1
+    o = _native.default_options()
+    o.schedule = 3
+    assert _call("learn", _problem(), o) == -1
+    o = _native.default_options()
+    o.kernel = 9
+    assert _call("sparse_code", _problem(), o) == -1
+    assert _call("tmod_update", _problem(), None, (0,)) == -1
+    assert _call("tmod_update", _problem(), None, (4,)) == -1
+    assert _call("learn", _problem(), None, (-1,)) == -1
+    assert _native.lib().sdl_sparse_code(None, 1, None, None) == -1
+    assert _native.lib().sdl_sparse_code(None, -1, None, None) == -1
+
+
+def test_default_options():
+    o = _native.default_options()
+    assert o.prec == 0 and o.use_graph == 1 and o.schedule == 0
+    assert o.stop_rel < 0 and o.dep_eps < 0 and o.pivot_fp64 < 0
