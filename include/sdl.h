@@ -125,6 +125,34 @@ int sdl_tmod_update(sdl_problem* p, int32_t nprob, uint32_t sides, const sdl_opt
 int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, const sdl_options* o,
               void* stream);
 
+/* Autotuner (no counterpart in the paper; a property of this GPU implementation):
+ * for every FP32 problem whose shape has register-resident kernel variants
+ * (different numbers of lanes per signal and register budgets), run each variant
+ * `reps` times on the problem's own signals, timed with HIP events on `stream`,
+ * and keep the fastest for all later calls in this process.  The problem's
+ * supp/coef/res2 are overwritten with valid codes.  If the environment variable
+ * SDL_TUNE_CACHE names a file, choices are loaded from it on first use and
+ * appended after tuning.  FP64 problems and shapes without variants are skipped.
+ * Synchronises. */
+int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_options* o, void* stream);
+
+/* Kernel configuration currently used for an FP32 shape: lanes per signal split
+ * over atom rows (lanes_row) and columns (lanes_col), register budget in waves
+ * per SIMD, and the tuned time in ms (0 if not tuned).  Returns 0 if the shape has
+ * a register-resident kernel, SDL_E_UNSUPPORTED if it runs on the generic kernel. */
+int sdl_tuned_config(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* lanes_row,
+                     int32_t* lanes_col, int32_t* waves_per_simd, double* ms);
+
+/* Register-resident kernel variants compiled for an FP32 shape: writes up to `cap`
+ * triples (lanes_row, lanes_col, waves_per_simd) to out (host, 3*cap int32) and
+ * returns how many exist (0: the shape runs on the generic kernel). */
+int sdl_kernel_variants(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* out, int32_t cap);
+
+/* Force the variant used for an FP32 shape for the rest of the process (instead of
+ * the autotuned or default one).  SDL_E_UNSUPPORTED if no such variant exists. */
+int sdl_set_kernel_variant(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t lanes_row,
+                           int32_t lanes_col, int32_t waves_per_simd);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* sdl_last_error(void);
 

@@ -67,6 +67,15 @@ def lib():
                                 ctypes.c_void_p]
         for f in (L.sdl_sparse_code, L.sdl_tmod_update, L.sdl_learn):
             f.restype = ctypes.c_int
+        L.sdl_autotune.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p]
+        L.sdl_autotune.restype = ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.sdl_tuned_config.argtypes = [ctypes.c_int32] * 5 + [ip, ip, ip, ctypes.POINTER(ctypes.c_double)]
+        L.sdl_tuned_config.restype = ctypes.c_int
+        L.sdl_kernel_variants.argtypes = [ctypes.c_int32] * 5 + [ip, ctypes.c_int32]
+        L.sdl_kernel_variants.restype = ctypes.c_int
+        L.sdl_set_kernel_variant.argtypes = [ctypes.c_int32] * 8
+        L.sdl_set_kernel_variant.restype = ctypes.c_int
         L.sdl_last_error.restype = ctypes.c_char_p
         L.sdl_last_error.argtypes = []
         L.sdl_abi_version.restype = ctypes.c_int

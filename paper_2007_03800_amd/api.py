@@ -137,5 +137,35 @@ def learn(problems: Problem | Sequence[Problem], K: int, stream=None, stats=None
     return trace[:len(problems)]
 
 
+def autotune(problems: Problem | Sequence[Problem], reps: int = 5, stream=None, **opts):
+    """Time the register-resident kernel variants on these problems and keep the fastest."""
+    problems = [problems] if isinstance(problems, Problem) else list(problems)
+    o = _options(problems, None, **opts)
+    arr = _array(problems)
+    _native.check(_native.lib().sdl_autotune(arr, len(problems), reps, ctypes.byref(o), _stream(stream)))
+
+
+def tuned_config(m1, m2, n1, n2, s):
+    """(lanes_row, lanes_col, waves_per_simd, tuned_ms) for an FP32 shape, or None (generic kernel)."""
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    ms = ctypes.c_double()
+    st = _native.lib().sdl_tuned_config(m1, m2, n1, n2, s, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                        ctypes.byref(ms))
+    if st != 0:
+        return None
+    return a.value, b.value, c.value, ms.value
+
+
+def kernel_variants(m1, m2, n1, n2, s):
+    """[(lanes_row, lanes_col, waves_per_simd), ...] compiled for an FP32 shape."""
+    buf = (ctypes.c_int32 * 192)()
+    n = _native.lib().sdl_kernel_variants(m1, m2, n1, n2, s, buf, 64)
+    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(min(n, 64))]
+
+
+def set_kernel_variant(m1, m2, n1, n2, s, variant):
+    _native.check(_native.lib().sdl_set_kernel_variant(m1, m2, n1, n2, s, *variant))
+
+
 def new_stats() -> _native.Stats:
     return _native.Stats()

@@ -1,17 +1,397 @@
-// Register-resident 2D-OMP for FP32 at fixed shapes (placeholder: no shapes yet).
+// Register-resident FP32 2D-OMP for fixed shapes (the image-patch workloads).
+//
+// Same method and Gram-form recurrences as omp_generic.hip (2D-OMP, Sec. III
+// step 1; Gram entries G1[i,i'] G2[j,j'], text after Algorithm 1), mapped for
+// CDNA4 throughput instead of generality:
+//
+//  * A group of LG = LR*LC consecutive lanes owns one signal; SPW = 64/LG signals
+//    run side by side in one wave64.  Lane (sr, sc) of a group holds the
+//    correlations of atoms (i, j) with i = sr + LR*ri, j = sc + LC*cj in
+//    registers (E = N1*N2/LG values), so the correlation refresh, the largest
+//    |corr| search and the first correlation are plain register arithmetic.
+//  * The Cholesky factor of the support Gram matrix, the coefficients and the
+//    support live in registers of every lane of the group (computed
+//    redundantly: free in SIMD); the shape and s are template parameters so the
+//    greedy loop is fully unrolled and every register index is static.
+//  * G1, G2, D1, D2 sit in LDS once per workgroup, with G1/G2 also stored in a
+//    lane-permuted order so each refresh term is two contiguous LDS reads.
+//  * Each signal's 2D block is staged through LDS with 16-byte coalesced loads.
+//  * Selected atoms are not masked explicitly: after the least-squares re-fit
+//    their correlation with the residual is zero up to rounding, so they cannot
+//    win while any unselected atom has a correlation above rounding level; if
+//    the search ever returns a selected atom the signal stops (same as the
+//    stop rule).  The FP64 reference masks explicitly; both agree whenever the
+//    stop threshold is above rounding level.
+//  * Pivots below pivot_fp64 * G_aa are recomputed in FP64 (cancellation in
+//    G_aa - |w|^2).
+#include <limits.h>
+
 #include "sdl_internal.h"
 
 namespace sdl {
+namespace {
 
-template <typename T>
-bool omp_fast_supported(int, int, int, int, int) { return false; }
+constexpr int kFastWaves = 4;  // waves per workgroup
 
-template <typename T>
-hipError_t launch_omp_fast(const OmpArgs<T>&, hipStream_t) { return hipErrorInvalidValue; }
+template <int M1_, int M2_, int N1_, int N2_, int S_, int LR_, int LC_, int WPE_>
+struct Cfg {
+  static constexpr int M1 = M1_, M2 = M2_, N1 = N1_, N2 = N2_, S = S_, LR = LR_, LC = LC_;
+  static constexpr int WPE = WPE_;  // register budget: target waves per SIMD (1 = unconstrained)
+  static constexpr int LG = LR * LC;
+  static constexpr int SPW = 64 / LG;
+  static constexpr int NRI = N1 / LR, NCJ = N2 / LC, E = NRI * NCJ;
+  static constexpr int M = M1 * M2;
+  // first correlation association: (D1^T Y) D2 when lanes split rows, D1^T (Y D2) when they split columns
+  static constexpr bool ROWFIRST = (NRI * M2 * M1 + E * M2) <= (NCJ * M1 * M2 + E * M1);
+  static constexpr int NL = S * (S + 1) / 2;
+  static_assert(N1 % LR == 0 && N2 % LC == 0 && 64 % LG == 0, "lane split must tile the atoms");
+  static_assert(M % 4 == 0, "signals are staged in 16-byte chunks");
+};
 
-template bool omp_fast_supported<float>(int, int, int, int, int);
-template bool omp_fast_supported<double>(int, int, int, int, int);
-template hipError_t launch_omp_fast<float>(const OmpArgs<float>&, hipStream_t);
-template hipError_t launch_omp_fast<double>(const OmpArgs<double>&, hipStream_t);
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int LG>
+__device__ inline float group_sum(float v) {
+#pragma unroll
+  for (int o = 1; o < LG; o <<= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+constexpr int tri(int k, int l) { return k * (k + 1) / 2 + l; }  // packed lower-triangular index
+
+template <class C>
+__global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE)))
+    omp_fast_kernel(OmpArgs<float> a) {
+  constexpr int M1 = C::M1, M2 = C::M2, N1 = C::N1, N2 = C::N2, S = C::S, LR = C::LR, LC = C::LC;
+  constexpr int LG = C::LG, SPW = C::SPW, NRI = C::NRI, NCJ = C::NCJ, E = C::E, M = C::M;
+  __shared__ float sG1[N1 * N1];
+  __shared__ float sG2[N2 * N2];
+  __shared__ __align__(16) float sG1P[N1 * N1];  // [ik][sr][ri] = G1[sr + LR*ri, ik]
+  __shared__ __align__(16) float sG2P[N2 * N2];  // [jk][sc][cj] = G2[jk, sc + LC*cj]
+  __shared__ __align__(16) float sD1[M1 * N1];
+  __shared__ __align__(16) float sD2[M2 * N2];
+  __shared__ __align__(16) float sY[kFastWaves][SPW * M];
+  __shared__ float sL[kFastWaves][SPW][C::NL];  // packed lower-triangular Cholesky factor per signal
+
+  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
+  const int g = lane / LG, sub = lane % LG, sr = sub / LC, sc = sub % LC;
+
+  for (int e = tid; e < N1 * N1; e += blockDim.x) {
+    sG1[e] = a.G1[e];
+    const int ik = e / N1, rem = e % N1, r_sr = rem / NRI, ri = rem % NRI;
+    sG1P[e] = a.G1[(r_sr + LR * ri) + N1 * ik];
+  }
+  for (int e = tid; e < N2 * N2; e += blockDim.x) {
+    sG2[e] = a.G2[e];
+    const int jk = e / N2, rem = e % N2, r_sc = rem / NCJ, cj = rem % NCJ;
+    sG2P[e] = a.G2[jk + N2 * (r_sc + LC * cj)];
+  }
+  for (int e = tid; e < M1 * N1; e += blockDim.x) sD1[e] = a.D1[e];
+  for (int e = tid; e < M2 * N2; e += blockDim.x) sD2[e] = a.D2[e];
+  __syncthreads();
+
+  const int lane_base = sr + N1 * sc;  // atom index of local element (ri, cj) = lane_base + LR*ri + N1*LC*cj
+  const float stop_rel = (float)a.stop_rel, dep_eps = (float)a.dep_eps, piv = (float)a.pivot_fp64;
+
+  const int64_t ngroups = (a.N + SPW - 1) / SPW;
+  float* ys = sY[wv];
+  for (int64_t grp = (int64_t)blockIdx.x * kFastWaves + wv; grp < ngroups; grp += (int64_t)gridDim.x * kFastWaves) {
+    const int64_t k0 = grp * SPW;
+    const int nvalid = (int)((a.N - k0) < SPW ? (a.N - k0) : SPW);
+    // ---- stage the wave's signals (contiguous) through LDS, 16-byte chunks
+    {
+      const float4* src = reinterpret_cast<const float4*>(a.Y + k0 * M);
+      float4* dst = reinterpret_cast<float4*>(ys);
+      const int nchunk = nvalid * M / 4;
+      for (int e = lane; e < SPW * M / 4; e += kWave)
+        dst[e] = e < nchunk ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    wave_sync();
+    const float* y = ys + g * M;
+    const bool valid = g < nvalid;
+
+    // ---- ||Y||_F and first correlation C = D1^T Y D2 (registers)
+    float yy = 0.f;
+#pragma unroll
+    for (int e = sub; e < M; e += LG) yy += y[e] * y[e];  // (runtime start; M/LG iterations)
+    const float ynorm = sqrtf(group_sum<LG>(yy));
+    float al[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) al[e] = 0.f;
+    if constexpr (C::ROWFIRST) {
+      // W = D1^T Y for this lane's rows (NRI x M2), then al = W D2
+#pragma unroll
+      for (int q = 0; q < M2; ++q) {
+        float w[NRI];
+#pragma unroll
+        for (int ri = 0; ri < NRI; ++ri) w[ri] = 0.f;
+#pragma unroll
+        for (int p = 0; p < M1; ++p) {
+          const float yv = y[p + M1 * q];
+#pragma unroll
+          for (int ri = 0; ri < NRI; ++ri) w[ri] += sD1[p + M1 * (sr + LR * ri)] * yv;
+        }
+#pragma unroll
+        for (int cj = 0; cj < NCJ; ++cj) {
+          const float d = sD2[q + M2 * (sc + LC * cj)];
+#pragma unroll
+          for (int ri = 0; ri < NRI; ++ri) al[cj * NRI + ri] += w[ri] * d;
+        }
+      }
+    } else {
+      // V = Y D2 for this lane's columns (M1 x NCJ), then al = D1^T V
+#pragma unroll
+      for (int p = 0; p < M1; ++p) {
+        float v[NCJ];
+#pragma unroll
+        for (int cj = 0; cj < NCJ; ++cj) v[cj] = 0.f;
+#pragma unroll
+        for (int q = 0; q < M2; ++q) {
+          const float yv = y[p + M1 * q];
+#pragma unroll
+          for (int cj = 0; cj < NCJ; ++cj) v[cj] += yv * sD2[q + M2 * (sc + LC * cj)];
+        }
+#pragma unroll
+        for (int ri = 0; ri < NRI; ++ri) {
+          const float d = sD1[p + M1 * (sr + LR * ri)];
+#pragma unroll
+          for (int cj = 0; cj < NCJ; ++cj) al[cj * NRI + ri] += d * v[cj];
+        }
+      }
+    }
+
+    // ---- greedy loop, fully unrolled over the support size
+    float* L = sL[wv][g];  // packed lower-triangular factor (diagonal unused; dinv holds 1/L_kk)
+    float dinv[S];
+    float x[S];
+    int ia[S], ja[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) { x[k] = 0.f; ia[k] = 0; ja[k] = 0; dinv[k] = 0.f; }
+    bool active = valid;
+    int nsel = 0;
+    const float stop_thr = stop_rel * ynorm;
+
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      // largest |corr| in this lane, scanning in increasing atom index (ties -> smallest)
+      float bv = -1.f, bs = 0.f;
+      int ba = 0;
+#pragma unroll
+      for (int cj = 0; cj < NCJ; ++cj)
+#pragma unroll
+        for (int ri = 0; ri < NRI; ++ri) {
+          const float v = al[cj * NRI + ri];
+          const float av = fabsf(v);
+          const bool c = av > bv;
+          bv = c ? av : bv;
+          bs = c ? v : bs;
+          ba = c ? (LR * ri + N1 * LC * cj) : ba;
+        }
+      ba += lane_base;
+#pragma unroll
+      for (int o = 1; o < LG; o <<= 1) {
+        const float ov = __shfl_xor(bv, o, kWave);
+        const float os = __shfl_xor(bs, o, kWave);
+        const int oa = __shfl_xor(ba, o, kWave);
+        const bool c = ov > bv || (ov == bv && oa < ba);
+        bv = c ? ov : bv;
+        bs = c ? os : bs;
+        ba = c ? oa : ba;
+      }
+      bool stop = !(bv > stop_thr);
+#pragma unroll
+      for (int k = 0; k < t; ++k) stop = stop || (ba == ia[k] + N1 * ja[k]);
+      if (stop) active = false;
+      const int it = ba % N1, jt = ba / N1;
+      float w[S > 1 ? S - 1 : 1];
+      float d2 = 0.f;
+      if (active) {
+        const float gaa = sG1[it + N1 * it] * sG2[jt + N2 * jt];
+        float ww = 0.f;
+#pragma unroll
+        for (int k = 0; k < t; ++k) {
+          float b = sG1[ia[k] + N1 * it] * sG2[ja[k] + N2 * jt];
+#pragma unroll
+          for (int l = 0; l < k; ++l) b -= L[tri(k, l)] * w[l];
+          w[k] = b * dinv[k];
+          ww += w[k] * w[k];
+        }
+        d2 = gaa - ww;
+        if (d2 < piv * gaa) {
+          // small pivot: this row again in FP64
+          double w64[S > 1 ? S - 1 : 1];
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < t; ++k) {
+            double b = (double)sG1[ia[k] + N1 * it] * (double)sG2[ja[k] + N2 * jt];
+#pragma unroll
+            for (int l = 0; l < k; ++l) b -= (double)L[tri(k, l)] * w64[l];
+            w64[k] = b * (double)dinv[k];
+            acc += w64[k] * w64[k];
+          }
+#pragma unroll
+          for (int k = 0; k < t; ++k) w[k] = (float)w64[k];
+          d2 = (float)((double)gaa - acc);
+          if (sub == 0) atomicAdd(&a.counters[kCtrFp64Pivot], 1ull);
+        }
+        if (!(d2 > dep_eps * gaa)) active = false;
+      }
+      if (active) {
+        // v = L^{-T} w ; coefficients x_S -= c v, x_t = c with c = corr_a / delta^2
+        float v[S > 1 ? S - 1 : 1];
+#pragma unroll
+        for (int k = t - 1; k >= 0; --k) {
+          float b = w[k];
+#pragma unroll
+          for (int l = k + 1; l < t; ++l) b -= L[tri(l, k)] * v[l];
+          v[k] = b * dinv[k];
+        }
+        const float cst = bs / d2;
+#pragma unroll
+        for (int k = 0; k < t; ++k) {
+          if (sub == 0) L[tri(t, k)] = w[k];
+          x[k] -= cst * v[k];
+        }
+        dinv[t] = rsqrtf(d2);
+        x[t] = cst;
+        ia[t] = it;
+        ja[t] = jt;
+        nsel = t + 1;
+        if (t + 1 < S) {
+          // corr <- corr - c * (G_{:,a} - G_{:,S} v): t+1 rank-one terms gamma_k g1_k g2_k^T
+#pragma unroll
+          for (int k = 0; k <= t; ++k) {
+            const float gk = k == t ? cst : -cst * v[k < t ? k : 0];
+            const int ik = k == t ? it : ia[k];
+            const int jk = k == t ? jt : ja[k];
+            float u[NRI], g2v[NCJ];
+            const float* g1p = sG1P + ik * N1 + sr * NRI;
+            const float* g2p = sG2P + jk * N2 + sc * NCJ;
+#pragma unroll
+            for (int ri = 0; ri < NRI; ++ri) u[ri] = gk * g1p[ri];
+#pragma unroll
+            for (int cj = 0; cj < NCJ; ++cj) g2v[cj] = g2p[cj];
+#pragma unroll
+            for (int cj = 0; cj < NCJ; ++cj)
+#pragma unroll
+              for (int ri = 0; ri < NRI; ++ri) al[cj * NRI + ri] -= u[ri] * g2v[cj];
+          }
+        }
+      }
+      wave_sync();
+    }
+
+    // ---- explicit residual and outputs
+    float rr = 0.f;
+#pragma unroll
+    for (int e0 = 0; e0 < M; e0 += LG) {
+      const int e = e0 + sub;
+      if (e < M) {
+        const int p = e % M1, q = e / M1;
+        float r = y[e];
+#pragma unroll
+        for (int k = 0; k < S; ++k) r -= x[k] * sD1[p + M1 * ia[k]] * sD2[q + M2 * ja[k]];
+        rr += r * r;
+      }
+    }
+    rr = group_sum<LG>(rr);
+    if (valid) {
+      const int64_t k = k0 + g;
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        if (t % LG == sub) {
+          a.supp[k * S + t] = t < nsel ? ia[t] + N1 * ja[t] : -1;
+          a.coef[k * S + t] = t < nsel ? x[t] : 0.f;
+        }
+      }
+      if (sub == 0) {
+        if (a.res2) a.res2[k] = rr;
+        if (nsel < S) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+      }
+    }
+    wave_sync();  // the staging buffer is rewritten by the next group
+  }
+}
+
+template <class C>
+hipError_t launch_cfg(const OmpArgs<float>& a, hipStream_t st) {
+  const int64_t ngroups = (a.N + C::SPW - 1) / C::SPW;
+  int64_t blocks = (ngroups + kFastWaves - 1) / kFastWaves;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(omp_fast_kernel<C>, dim3((unsigned)blocks), dim3(kWave * kFastWaves), 0, st, a);
+  return hipGetLastError();
+}
+
+// Register-resident instantiations: shape (m1, m2, n1, n2, s) and the variants the
+// autotuner chooses from (lane split LR x LC, register budget in waves per SIMD).
+#define SDL_FAST_VARIANTS(X)                                                        \
+  X(8, 8, 16, 16, 8, 1, 4, 1) X(8, 8, 16, 16, 8, 1, 4, 2) X(8, 8, 16, 16, 8, 2, 4, 2) \
+  X(8, 8, 16, 16, 8, 2, 4, 3) X(8, 8, 16, 16, 6, 1, 4, 2) X(8, 8, 16, 16, 6, 2, 4, 3) \
+  X(8, 8, 12, 12, 4, 1, 4, 3) X(12, 12, 20, 20, 10, 1, 4, 1) X(12, 12, 20, 20, 10, 2, 4, 2) \
+  X(12, 12, 24, 24, 12, 2, 4, 1) X(12, 12, 24, 24, 12, 4, 4, 2) \
+  X(16, 16, 32, 32, 16, 4, 4, 1) X(16, 16, 32, 32, 16, 4, 8, 2)
+
+struct Variant {
+  int m1, m2, n1, n2, s, lr, lc, wpe;
+  hipError_t (*launch)(const OmpArgs<float>&, hipStream_t);
+};
+
+const Variant kVariants[] = {
+#define X(A_, B_, C_, D_, E_, F_, G_, H_) {A_, B_, C_, D_, E_, F_, G_, H_, &launch_cfg<Cfg<A_, B_, C_, D_, E_, F_, G_, H_>>},
+    SDL_FAST_VARIANTS(X)
+#undef X
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+}  // namespace
+
+template <>
+bool omp_fast_supported<float>(int m1, int m2, int n1, int n2, int s) {
+  return omp_fast_variants(m1, m2, n1, n2, s, nullptr, 0) > 0;
+}
+
+template <>
+bool omp_fast_supported<double>(int, int, int, int, int) {
+  return false;
+}
+
+int omp_fast_variants(int m1, int m2, int n1, int n2, int s, int* ids, int cap) {
+  int n = 0;
+  for (int v = 0; v < kNumVariants; ++v) {
+    const Variant& x = kVariants[v];
+    if (x.m1 == m1 && x.m2 == m2 && x.n1 == n1 && x.n2 == n2 && x.s == s) {
+      if (ids && n < cap) ids[n] = v;
+      ++n;
+    }
+  }
+  return n;
+}
+
+void omp_fast_variant_info(int id, int* lr, int* lc, int* wpe) {
+  *lr = kVariants[id].lr;
+  *lc = kVariants[id].lc;
+  *wpe = kVariants[id].wpe;
+}
+
+hipError_t launch_omp_fast_variant(int id, const OmpArgs<float>& a, hipStream_t st) {
+  if (id < 0 || id >= kNumVariants) return hipErrorInvalidValue;
+  if (a.N == 0) return hipSuccess;
+  return kVariants[id].launch(a, st);
+}
+
+template <>
+hipError_t launch_omp_fast<float>(const OmpArgs<float>& a, hipStream_t st) {
+  return launch_omp_fast_variant(omp_fast_choice(a.m1, a.m2, a.n1, a.n2, a.s), a, st);
+}
+
+template <>
+hipError_t launch_omp_fast<double>(const OmpArgs<double>&, hipStream_t) {
+  return hipErrorInvalidValue;
+}
 
 }  // namespace sdl

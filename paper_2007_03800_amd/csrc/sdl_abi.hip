@@ -548,6 +548,71 @@ int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, cons
                               : learn_impl<float>(p, nprob, K, rmse_trace, opt, st);
 }
 
+int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_options* o, void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  opt.prec = SDL_FP32;
+  SDL_TRY(validate(p, nprob, opt, false));
+  if (reps < 1) return fail(SDL_E_INVAL, "reps = %d < 1", reps);
+  hipStream_t st = (hipStream_t)stream;
+  Ctx* ctx;
+  SDL_TRY(get_ctx(st, &ctx));
+  Plan pl;
+  layout(p, nprob, sizeof(float), 0, nullptr, &pl);
+  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
+  layout(p, nprob, sizeof(float), 0, ctx->ws, &pl);
+  std::vector<std::pair<int, int>> marks;
+  Launcher L{st, false, ctx, &marks};
+  SDL_TRY(begin_call(st, ctx, pl, nprob));
+  for (int q = 0; q < nprob; ++q) {
+    if (p[q].N == 0 || !omp_fast_supported<float>(p[q].m1, p[q].m2, p[q].n1, p[q].n2, p[q].s)) continue;
+    SDL_TRY(run_prep<float>(p[q], pl.pb[q], L));
+    OmpArgs<float> a = omp_args<float>(p[q], pl.pb[q], opt, pl);
+    int id;
+    double ms;
+    HIP_TRY(autotune_problem(a, st, reps, &id, &ms));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return SDL_OK;
+}
+
+int sdl_tuned_config(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* lanes_row,
+                     int32_t* lanes_col, int32_t* waves_per_simd, double* ms) {
+  int lr = 0, lc = 0, wpe = 0;
+  double t = 0.0;
+  if (!tuned_config(m1, m2, n1, n2, s, &lr, &lc, &wpe, &t))
+    return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for this shape");
+  if (lanes_row) *lanes_row = lr;
+  if (lanes_col) *lanes_col = lc;
+  if (waves_per_simd) *waves_per_simd = wpe;
+  if (ms) *ms = t;
+  return SDL_OK;
+}
+
+int sdl_kernel_variants(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* out, int32_t cap) {
+  int ids[64];
+  const int n = omp_fast_variants(m1, m2, n1, n2, s, ids, 64);
+  for (int i = 0; i < n && i < cap && i < 64 && out; ++i)
+    omp_fast_variant_info(ids[i], &out[3 * i], &out[3 * i + 1], &out[3 * i + 2]);
+  return n;
+}
+
+int sdl_set_kernel_variant(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t lanes_row,
+                           int32_t lanes_col, int32_t waves_per_simd) {
+  int ids[64];
+  const int n = omp_fast_variants(m1, m2, n1, n2, s, ids, 64);
+  for (int i = 0; i < n && i < 64; ++i) {
+    int lr, lc, wpe;
+    omp_fast_variant_info(ids[i], &lr, &lc, &wpe);
+    if (lr == lanes_row && lc == lanes_col && wpe == waves_per_simd) {
+      omp_fast_set_choice(m1, m2, n1, n2, s, ids[i]);
+      return SDL_OK;
+    }
+  }
+  return fail(SDL_E_UNSUPPORTED, "no kernel variant (%d, %d, %d) for this shape", lanes_row, lanes_col,
+              waves_per_simd);
+}
+
 const char* sdl_last_error(void) { return g_err.c_str(); }
 
 int sdl_abi_version(void) { return SDL_ABI_VERSION; }

@@ -53,6 +53,15 @@ template <typename T>
 bool omp_fast_supported(int m1, int m2, int n1, int n2, int s);
 template <typename T>
 hipError_t launch_omp_fast(const OmpArgs<T>& a, hipStream_t st);
+// Register-resident variants for a shape: writes up to cap variant ids, returns the count.
+int omp_fast_variants(int m1, int m2, int n1, int n2, int s, int* ids, int cap);
+void omp_fast_variant_info(int id, int* lr, int* lc, int* wpe);
+hipError_t launch_omp_fast_variant(int id, const OmpArgs<float>& a, hipStream_t st);
+// Variant used for a shape: the autotuned one if tuned in this process, else the first listed.
+int omp_fast_choice(int m1, int m2, int n1, int n2, int s);
+void omp_fast_set_choice(int m1, int m2, int n1, int n2, int s, int id);
+hipError_t autotune_problem(const OmpArgs<float>& a, hipStream_t st, int reps, int* chosen, double* best_ms);
+bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* wpe, double* ms);
 size_t omp_generic_lds_bytes(int m1, int m2, int n1, int n2, int s, size_t elem);
 hipError_t omp_generic_init_device();
 
