@@ -58,6 +58,7 @@ int get_ctx(hipStream_t st, Ctx** out) {
     Ctx* c = new Ctx();
     c->device = dev;
     hipError_t e = omp_generic_init_device();
+    if (e == hipSuccess) e = tmod_sums_init_device();
     if (e != hipSuccess) {
       delete c;
       return fail(SDL_E_DEVICE, "kernel attribute setup: %s", hipGetErrorString(e));
@@ -198,7 +199,8 @@ void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Pla
     x.G2c = b.take<char>(elem * r.n2 * r.n2);
     const int na = r.n1 > r.n2 ? r.n1 : r.n2, mr = r.m1 > r.m2 ? r.m1 : r.m2;
     x.nent = na * na + mr * na;
-    x.nblk = tmod_num_blocks(r.N);
+    const int nb1 = tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2), nb2 = tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1);
+    x.nblk = nb1 > nb2 ? nb1 : nb2;
     x.rblk = rmse_num_blocks(r.N);
     x.part = b.take<double>((size_t)x.nblk * x.nent);
     x.sums = b.take<double>((size_t)x.nent);
@@ -297,10 +299,11 @@ int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bo
   const int na = side == 1 ? r.n1 : r.n2, mr = side == 1 ? r.m1 : r.m2;
   const int nent = na * na + mr * na;
   SDL_TRY(L.begin(1));
-  HIP_TRY(launch_tmod_sums<T>(a, b.part, b.nblk, L.st));
+  const int nblk = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2) : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1);
+  HIP_TRY(launch_tmod_sums<T>(a, b.part, nblk, L.st));
   SDL_TRY(L.end());
   SDL_TRY(L.begin(2));
-  HIP_TRY(launch_reduce_partials(b.part, b.nblk, nent, b.sums, L.st));
+  HIP_TRY(launch_reduce_partials(b.part, nblk, nent, b.sums, L.st));
   SDL_TRY(L.end());
   SDL_TRY(L.begin(3));
   if (side == 1)

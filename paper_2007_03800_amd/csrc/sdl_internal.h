@@ -65,8 +65,9 @@ bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* 
 size_t omp_generic_lds_bytes(int m1, int m2, int n1, int n2, int s, size_t elem);
 hipError_t omp_generic_init_device();
 
-// Number of per-block partials used by the sums kernel for N signals (fixed function of N).
-int tmod_num_blocks(int64_t N);
+// Number of workgroup partials of the sums kernel (a fixed function of N and the shape).
+int tmod_num_blocks_for(int64_t N, int na, int mr, int mc);
+hipError_t tmod_sums_init_device();
 template <typename T>
 hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, int nblk, hipStream_t st);
 hipError_t launch_reduce_partials(const double* part, int nblk, int nent, double* out, hipStream_t st);

@@ -20,91 +20,21 @@
 namespace sdl {
 namespace {
 
-constexpr int kSumThreads = 256;
-constexpr int kMaxEntPerThread = 32;  // (na^2 + mr*na) / 256 for na, mr <= 64
-
-template <typename T>
-__global__ void __launch_bounds__(kSumThreads) tmod_sums_kernel(TmodArgs<T> a, double* part, int nblk, int bs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
-  const int side = a.side, n1 = a.n1, s = a.s;
-  const int na = side == 1 ? a.n1 : a.n2;
-  const int mr = side == 1 ? a.m1 : a.m2;  // rows of Yt
-  const int mc = side == 1 ? a.m2 : a.m1;  // cols of Yt (= rows of Do)
-  const int M = a.m1 * a.m2;
-  const int nent = na * na + mr * na;
-  T* Tb = sm;                    // bs x na x mc
-  T* Yb = Tb + bs * na * mc;     // bs x mr x mc  (Yt[r][c] at r*mc + c)
-  const int tid = threadIdx.x;
-  const int64_t k0 = (a.N * blockIdx.x) / nblk, k1 = (a.N * (blockIdx.x + 1)) / nblk;
-
-  T acc[kMaxEntPerThread];
-#pragma unroll
-  for (int u = 0; u < kMaxEntPerThread; ++u) acc[u] = 0;
-
-  for (int64_t kb = k0; kb < k1; kb += bs) {
-    const int nb = (int)((k1 - kb) < bs ? (k1 - kb) : bs);
-    for (int e = tid; e < bs * na * mc; e += kSumThreads) Tb[e] = 0;
-    for (int e = tid; e < bs * M; e += kSumThreads) {
-      const int b = e / M, pix = e % M;
-      T v = 0;
-      if (b < nb) v = a.Y[(kb + b) * M + pix];
-      const int p = pix % a.m1, q = pix / a.m1;  // Y[p, q]
-      const int r = side == 1 ? p : q, c = side == 1 ? q : p;
-      Yb[b * mr * mc + r * mc + c] = v;
-    }
-    __syncthreads();
-    for (int e = tid; e < nb * mc; e += kSumThreads) {
-      const int b = e / mc, c = e % mc;
-      const int64_t k = kb + b;
-      for (int t = 0; t < s; ++t) {
-        const int at = a.supp[k * s + t];
-        if (at < 0) continue;
-        const int i = at % n1, j = at / n1;
-        const int ra = side == 1 ? i : j, rb = side == 1 ? j : i;
-        Tb[(b * na + ra) * mc + c] += a.coef[k * s + t] * a.Dother[c + mc * rb];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kMaxEntPerThread; ++u) {
-      const int e = tid + u * kSumThreads;
-      if (e < nent) {
-        T v = acc[u];
-        if (e < na * na) {
-          const int r1 = e % na, r2 = e / na;
-          for (int b = 0; b < nb; ++b) {
-            const T* t1 = Tb + (b * na + r1) * mc;
-            const T* t2 = Tb + (b * na + r2) * mc;
-            for (int c = 0; c < mc; ++c) v += t1[c] * t2[c];
-          }
-        } else {
-          const int f = e - na * na;
-          const int r = f % mr, ra = f / mr;
-          for (int b = 0; b < nb; ++b) {
-            const T* yr = Yb + b * mr * mc + r * mc;
-            const T* tr = Tb + (b * na + ra) * mc;
-            for (int c = 0; c < mc; ++c) v += yr[c] * tr[c];
-          }
-        }
-        acc[u] = v;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < kMaxEntPerThread; ++u) {
-    const int e = tid + u * kSumThreads;
-    if (e < nent) part[(size_t)blockIdx.x * nent + e] = (double)acc[u];
-  }
-}
-
-__global__ void reduce_partials_kernel(const double* __restrict__ part, int nblk, int nent, double* out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nent) return;
+// out[e] = sum over workgroup partials b of part[b][e], in a fixed order: four
+// interleaved stripes per entry, then the stripes in order.
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const double* __restrict__ part, int nblk, int nent,
+                                                              double* out) {
+  __shared__ double red[4][64];
+  const int el = threadIdx.x % 64, stripe = threadIdx.x / 64;
+  const int e = blockIdx.x * 64 + el;
   double v = 0.0;
-  for (int b = 0; b < nblk; ++b) v += part[(size_t)b * nent + e];
-  out[e] = v;
+  if (e < nent) {
+#pragma unroll 8
+    for (int b = stripe; b < nblk; b += 4) v += part[(size_t)b * nent + e];
+  }
+  red[stripe][el] = v;
+  __syncthreads();
+  if (stripe == 0 && e < nent) out[e] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
 }
 
 // D (mr x na FP64) -> compute-type copy, FP64 and compute-type Gram D^T D.
@@ -125,97 +55,109 @@ __global__ void dict_prep_kernel(const double* D, int mr, int na, T* Dc, double*
   write_copies<T>(D, mr, na, Dc, G64, Gc);
 }
 
-constexpr int kSolveThreads = 256;
 constexpr double kSpdRelTol = 1e-12;  // pivot <= tol * diagonal entry -> not positive definite
+constexpr int kLd = SDL_MAX_N + 1;     // padded LDS row length
 
-// sums = [A (na x na) | B (mr x na)], both column-major.
+__device__ inline void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront: FP64 Cholesky of the Gram sum on the used atoms, two triangular
+// solves with mr right-hand sides, normalisation.  sums = [A (na x na) | B (mr x na)],
+// column-major.  All steps are wave-synchronous (no workgroup barriers).
 template <typename T>
-__global__ void __launch_bounds__(kSolveThreads)
+__global__ void __launch_bounds__(64)
     tmod_solve_kernel(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
                       int* status, unsigned long long* counters) {
-  __shared__ double C[SDL_MAX_N * SDL_MAX_N];
-  __shared__ double Xs[SDL_MAX_M * SDL_MAX_N];  // solution D*, mr x na column-major
+  __shared__ double C[SDL_MAX_N * kLd];
+  __shared__ double X[SDL_MAX_N * kLd];  // X[k][p]: right-hand sides / solution, atom k, row p
   __shared__ double diag0[SDL_MAX_N];
   __shared__ int U[SDL_MAX_N];
-  __shared__ int nu_s, bad_s;
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   const double* A = sums;
   const double* B = sums + na * na;
-  if (tid == 0) {
-    int nu = 0;
-    for (int i = 0; i < na; ++i)
-      if (A[i + na * i] > 0.0) U[nu++] = i;
-    nu_s = nu;
-    bad_s = 0;
-    if (nu < na) atomicAdd(&counters[kCtrUnusedAtoms], (unsigned long long)(na - nu));
-  }
-  __syncthreads();
-  const int nu = nu_s;
-  // compacted Gram sum on the used atoms (the system decouples exactly for unused ones)
-  for (int e = tid; e < nu * nu; e += kSolveThreads) {
+  // used atoms (positive diagonal), compacted in index order with a ballot
+  const bool used = lane < na && A[lane + na * lane] > 0.0;
+  const unsigned long long mask = __ballot(used);
+  const int nu = __popcll(mask);
+  if (used) U[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
+  if (lane == 0 && nu < na) atomicAdd(&counters[kCtrUnusedAtoms], (unsigned long long)(na - nu));
+  wsync();
+  for (int e = lane; e < nu * nu; e += 64) {
     const int k = e % nu, l = e / nu;
-    C[k * nu + l] = A[U[k] + na * U[l]];
-    if (k == l) diag0[k] = A[U[k] + na * U[k]];
+    C[k * kLd + l] = A[U[k] + na * U[l]];
+    if (k == l) diag0[k] = C[k * kLd + k];
   }
-  __syncthreads();
-  // right-looking Cholesky, lower triangle of C (row-major, ld nu)
-  for (int k = 0; k < nu; ++k) {
-    if (tid == 0) {
-      const double d = C[k * nu + k];
-      if (!(d > kSpdRelTol * diag0[k])) bad_s = 1;
-      else C[k * nu + k] = sqrt(d);
+  for (int e = lane; e < nu * mr; e += 64) {
+    const int k = e % nu, p = e / nu;
+    X[k * kLd + p] = B[p + mr * U[k]];
+  }
+  wsync();
+  bool bad = false;
+  for (int k = 0; k < nu && !bad; ++k) {
+    const double d = C[k * kLd + k];
+    if (!(d > kSpdRelTol * diag0[k])) {
+      bad = true;
+      break;
     }
-    __syncthreads();
-    if (bad_s) break;
-    const double lkk = C[k * nu + k];
-    for (int i = k + 1 + tid; i < nu; i += kSolveThreads) C[i * nu + k] /= lkk;
-    __syncthreads();
+    const double lkk = sqrt(d), inv = 1.0 / lkk;
+    wsync();
+    if (lane == 0) C[k * kLd + k] = lkk;
+    for (int i = k + 1 + lane; i < nu; i += 64) C[i * kLd + k] *= inv;
+    wsync();
     const int rem = nu - k - 1;
-    for (int e = tid; e < rem * rem; e += kSolveThreads) {
+    for (int e = lane; e < rem * rem; e += 64) {
       const int i = k + 1 + e % rem, j = k + 1 + e / rem;
-      if (j <= i) C[i * nu + j] -= C[i * nu + k] * C[j * nu + k];
+      if (j <= i) C[i * kLd + j] -= C[i * kLd + k] * C[j * kLd + k];
     }
-    __syncthreads();
+    wsync();
   }
-  const bool bad = bad_s != 0;
   if (!bad) {
-    // D* A_UU = B_U  <=>  A_UU (row p of D*)^T = (row p of B_U)^T; one thread per row p
-    for (int p = tid; p < mr; p += kSolveThreads) {
-      double* x = Xs + p;  // stride mr over atoms
-      for (int k = 0; k < nu; ++k) {
-        double v = B[p + mr * U[k]];
-        for (int l = 0; l < k; ++l) v -= C[k * nu + l] * x[mr * l];
-        x[mr * k] = v / C[k * nu + k];
+    // L Z = X (forward), then L^T X = Z (backward); columns p in parallel
+    for (int k = 0; k < nu; ++k) {
+      const double inv = 1.0 / C[k * kLd + k];
+      for (int p = lane; p < mr; p += 64) X[k * kLd + p] *= inv;
+      wsync();
+      for (int e = lane; e < (nu - k - 1) * mr; e += 64) {
+        const int i = k + 1 + e / mr, p = e % mr;
+        X[i * kLd + p] -= C[i * kLd + k] * X[k * kLd + p];
       }
-      for (int k = nu - 1; k >= 0; --k) {
-        double v = x[mr * k];
-        for (int l = k + 1; l < nu; ++l) v -= C[l * nu + k] * x[mr * l];
-        x[mr * k] = v / C[k * nu + k];
-      }
+      wsync();
     }
-    __syncthreads();
-    // normalise the solved atoms (W); zero or unused columns keep the old atom
-    for (int i = tid; i < na; i += kSolveThreads) w[i] = 1.0;
-    __syncthreads();
-    for (int k = tid; k < nu; k += kSolveThreads) {
+    for (int k = nu - 1; k >= 0; --k) {
+      const double inv = 1.0 / C[k * kLd + k];
+      for (int p = lane; p < mr; p += 64) X[k * kLd + p] *= inv;
+      wsync();
+      for (int e = lane; e < k * mr; e += 64) {
+        const int i = e / mr, p = e % mr;
+        X[i * kLd + p] -= C[k * kLd + i] * X[k * kLd + p];
+      }
+      wsync();
+    }
+    // normalisation W: unit-norm columns; a zero column keeps the old atom; unused atoms kept
+    for (int i = lane; i < na; i += 64) w[i] = 1.0;
+    wsync();
+    for (int k = lane; k < nu; k += 64) {
       const int i = U[k];
       double nrm = 0.0;
-      for (int p = 0; p < mr; ++p) nrm += Xs[p + mr * k] * Xs[p + mr * k];
+      for (int p = 0; p < mr; ++p) nrm += X[k * kLd + p] * X[k * kLd + p];
       nrm = sqrt(nrm);
       if (nrm > 0.0) {
         w[i] = nrm;
-        for (int p = 0; p < mr; ++p) D[p + mr * i] = Xs[p + mr * k] / nrm;
+        for (int p = 0; p < mr; ++p) D[p + mr * i] = X[k * kLd + p] / nrm;
       }
     }
   } else {
-    for (int i = tid; i < na; i += kSolveThreads) w[i] = 1.0;
-    if (tid == 0) {
+    for (int i = lane; i < na; i += 64) w[i] = 1.0;
+    if (lane == 0) {
       atomicOr(status, kStatusSingular);
       atomicAdd(&counters[kCtrSingular], 1ull);
     }
   }
   __threadfence_block();
-  __syncthreads();
+  wsync();
   write_copies<T>(D, mr, na, Dc, G64, Gc);
 }
 
@@ -274,37 +216,15 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
 
 }  // namespace
 
-int tmod_num_blocks(int64_t N) {
-  // ~64+ signals per workgroup, at most 2048 workgroups (8 per CU)
-  int64_t b = (N + 63) / 64;
-  if (b > 2048) b = 2048;
-  if (b < 1) b = 1;
-  return (int)b;
-}
-
-template <typename T>
-hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, int nblk, hipStream_t st) {
-  const int na = a.side == 1 ? a.n1 : a.n2;
-  const int mr = a.side == 1 ? a.m1 : a.m2;
-  const int mc = a.side == 1 ? a.m2 : a.m1;
-  const int per = na * mc + mr * mc;  // elements per staged signal
-  int bs = (int)(32768 / (per * sizeof(T)));
-  if (bs > 16) bs = 16;
-  if (bs < 1) bs = 1;
-  const size_t lds = (size_t)bs * per * sizeof(T);
-  hipLaunchKernelGGL(tmod_sums_kernel<T>, dim3(nblk), dim3(kSumThreads), lds, st, a, part, nblk, bs);
-  return hipGetLastError();
-}
-
 hipError_t launch_reduce_partials(const double* part, int nblk, int nent, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nent + 255) / 256), dim3(256), 0, st, part, nblk, nent, out);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nent + 63) / 64), dim3(256), 0, st, part, nblk, nent, out);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_tmod_solve(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
                              int* status, unsigned long long* counters, hipStream_t st) {
-  hipLaunchKernelGGL(tmod_solve_kernel<T>, dim3(1), dim3(kSolveThreads), 0, st, sums, mr, na, D, Dc, G64, Gc, w,
+  hipLaunchKernelGGL(tmod_solve_kernel<T>, dim3(1), dim3(64), 0, st, sums, mr, na, D, Dc, G64, Gc, w,
                      status, counters);
   return hipGetLastError();
 }
@@ -355,7 +275,6 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st) {
 }
 
 #define SDL_INST(T)                                                                                            \
-  template hipError_t launch_tmod_sums<T>(const TmodArgs<T>&, double*, int, hipStream_t);                    \
   template hipError_t launch_tmod_solve<T>(const double*, int, int, double*, T*, double*, T*, double*, int*,  \
                                            unsigned long long*, hipStream_t);                                 \
   template hipError_t launch_dict_prep<T>(const double*, int, int, T*, double*, T*, hipStream_t);             \
