@@ -79,8 +79,9 @@ typedef struct sdl_stats {
   int64_t unused_atoms;     /* atoms kept unchanged because no code used them */
   int64_t singular_updates; /* dictionary updates skipped as not positive definite */
   /* Per-kernel device time when sdl_options.timing = 1, measured with HIP events on
-   * the call's stream.  Index: 0 sparse coding, 1 TMOD sums, 2 partial reduction,
-   * 3 solve+normalise, 4 dictionary prep, 5 RMSE, 6 code rescale. */
+   * the call's stream.  Index: 0 sparse coding (on the FP32 register-resident path it
+   * also accumulates the next update's sums), 1 standalone TMOD sums, 2 fixed-order
+   * reduction, 3 FP64 solve + normalise, 4 dictionary prep, 5 RMSE, 6 code rescale. */
   double kernel_ms[8];
   int64_t kernel_launches[8];
 } sdl_stats;

@@ -32,6 +32,9 @@ namespace sdl {
 namespace {
 
 constexpr int kFastWaves = 4;  // waves per workgroup
+constexpr int kFastMaxBlocks = 1024;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int M1_, int M2_, int N1_, int N2_, int S_, int LR_, int LC_, int WPE_>
 struct Cfg {
@@ -44,6 +47,21 @@ struct Cfg {
   // first correlation association: (D1^T Y) D2 when lanes split rows, D1^T (Y D2) when they split columns
   static constexpr bool ROWFIRST = (NRI * M2 * M1 + E * M2) <= (NCJ * M1 * M2 + E * M1);
   static constexpr int NL = S * (S + 1) / 2;
+  // epilogue TMOD sums: tiles over either side's atoms / signal rows, signals per MFMA pass
+  static constexpr int NAX = N1 > N2 ? N1 : N2, MRX = M1 > M2 ? M1 : M2;
+  static constexpr int TPX = (NAX + 15) / 16, TRX = (MRX + 15) / 16, NPX = 16 * TPX + 1;
+  // signals per epilogue pass: keep the per-wave Tcat near 8 KiB
+  static constexpr int SUB = (SPW * MRX * NPX <= 2048) ? SPW
+                             : (SPW / 2 * MRX * NPX <= 2048 || SPW / 2 <= 1) ? (SPW / 2 > 0 ? SPW / 2 : 1)
+                             : (SPW / 4 * MRX * NPX <= 2048 || SPW / 4 <= 1) ? (SPW / 4 > 0 ? SPW / 4 : 1)
+                             : (SPW / 8 > 0 ? SPW / 8 : 1);
+  // per-wave LDS work area: the Cholesky factors during the greedy loop, Tcat in the epilogue
+  static constexpr int WORK = SPW * NL > SUB * MRX * NPX ? SPW * NL : SUB * MRX * NPX;
+  // epilogue accumulators live in LDS between groups: (TPX*TPX + TRX*TPX) tiles x 4 values x 64 lanes
+  static constexpr int NTILE = TPX * TPX + TRX * TPX;
+  // block reduction buffer (kFastWaves rows of the largest side's entry count + 1), aliased on the staging area
+  static constexpr int NENTX = NAX * NAX + MRX * NAX + 1;
+  static constexpr int STAGE = (SPW * M * 4 > NENTX * 4) ? SPW * M : NENTX;
   static_assert(N1 % LR == 0 && N2 % LC == 0 && 64 % LG == 0, "lane split must tile the atoms");
   static_assert(M % 4 == 0, "signals are staged in 16-byte chunks");
 };
@@ -74,8 +92,12 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
   __shared__ __align__(16) float sG2P[N2 * N2];  // [jk][sc][cj] = G2[jk, sc + LC*cj]
   __shared__ __align__(16) float sD1[M1 * N1];
   __shared__ __align__(16) float sD2[M2 * N2];
-  __shared__ __align__(16) float sY[kFastWaves][SPW * M];
-  __shared__ float sL[kFastWaves][SPW][C::NL];  // packed lower-triangular Cholesky factor per signal
+  __shared__ __align__(16) float sY[kFastWaves][C::STAGE];
+  // per wave: packed lower-triangular Cholesky factors of its signals (greedy loop), then
+  // Tcat with one column per (signal, c) (epilogue); the two phases are separated by a wave sync
+  __shared__ float sWork[kFastWaves][C::WORK];
+  __shared__ float sAcc[kFastWaves][C::NTILE * 4 * kWave];  // epilogue accumulators, lane-major
+  __shared__ double sRacc[kFastWaves];
 
   const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
   const int g = lane / LG, sub = lane % LG, sr = sub / LC, sc = sub % LC;
@@ -99,6 +121,14 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
 
   const int64_t ngroups = (a.N + SPW - 1) / SPW;
   float* ys = sY[wv];
+  // epilogue accumulators (the next dictionary update's sums and sum of res2)
+  const int eside = a.sums_side;
+  const int ena = eside == 2 ? N2 : N1, emr = eside == 2 ? M2 : M1, emc = eside == 2 ? M1 : M2;
+  const float* eDo = eside == 2 ? sD1 : sD2;  // fixed dictionary: emc x (other atoms), column-major
+  f32x4* acc = reinterpret_cast<f32x4*>(sAcc[wv]) + lane;  // tile q of this lane at acc[q * kWave]
+#pragma unroll
+  for (int q = 0; q < C::NTILE; ++q) acc[q * kWave] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double racc = 0.0;
   for (int64_t grp = (int64_t)blockIdx.x * kFastWaves + wv; grp < ngroups; grp += (int64_t)gridDim.x * kFastWaves) {
     const int64_t k0 = grp * SPW;
     const int nvalid = (int)((a.N - k0) < SPW ? (a.N - k0) : SPW);
@@ -165,7 +195,7 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
     }
 
     // ---- greedy loop, fully unrolled over the support size
-    float* L = sL[wv][g];  // packed lower-triangular factor (diagonal unused; dinv holds 1/L_kk)
+    float* L = sWork[wv] + g * C::NL;  // packed lower-triangular factor (diagonal unused; dinv holds 1/L_kk)
     float dinv[S];
     float x[S];
     int ia[S], ja[S];
@@ -311,18 +341,132 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
       if (sub == 0) {
         if (a.res2) a.res2[k] = rr;
         if (nsel < S) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+        racc += (double)rr;
       }
+    }
+    if (eside) {
+      // Tcat = [T_1 .. T_SUB] for side 1 (T = X D2^T) or side 2 (T = (D1 X)^T), one
+      // column per (signal, c); then A += Tcat Tcat^T, B += Ycat Tcat^T on the matrix cores
+      const int r16 = lane % 16, kq = lane / 16;
+      float* tc = sWork[wv];
+      f32x4 accP[C::TPX][C::TPX], accR[C::TRX][C::TPX];
+#pragma unroll
+      for (int i = 0; i < C::TPX; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TPX; ++j) accP[i][j] = acc[(i * C::TPX + j) * kWave];
+#pragma unroll
+      for (int i = 0; i < C::TRX; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TPX; ++j) accR[i][j] = acc[(C::TPX * C::TPX + i * C::TPX + j) * kWave];
+#pragma unroll
+      for (int pass = 0; pass < SPW; pass += C::SUB) {
+        if (g >= pass && g < pass + C::SUB) {
+          for (int c = sub; c < emc; c += LG) {
+            float* col = tc + ((g - pass) * emc + c) * C::NPX;
+            for (int r = 0; r < C::NPX; ++r) col[r] = 0.f;
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+              const int ra = eside == 1 ? ia[t] : ja[t], rb = eside == 1 ? ja[t] : ia[t];
+              col[ra] += x[t] * eDo[c + emc * rb];
+            }
+          }
+        }
+        wave_sync();
+        for (int kk = 0; kk < C::SUB * emc; kk += 4) {
+          const int kx = kk + kq;
+          const int b = pass + kx / emc, c = kx % emc;
+          float at[C::TPX], ay[C::TRX];
+#pragma unroll
+          for (int i = 0; i < C::TPX; ++i) at[i] = tc[kx * C::NPX + 16 * i + r16];
+#pragma unroll
+          for (int i = 0; i < C::TRX; ++i) {
+            const int row = 16 * i + r16;
+            ay[i] = row < emr ? (eside == 1 ? ys[b * M + c * M1 + row] : ys[b * M + c + M1 * row]) : 0.f;
+          }
+#pragma unroll
+          for (int i = 0; i < C::TPX; ++i)
+#pragma unroll
+            for (int j = 0; j < C::TPX; ++j)
+              accP[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(at[i], at[j], accP[i][j], 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < C::TRX; ++i)
+#pragma unroll
+            for (int j = 0; j < C::TPX; ++j)
+              accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ay[i], at[j], accR[i][j], 0, 0, 0);
+        }
+        wave_sync();
+      }
+#pragma unroll
+      for (int i = 0; i < C::TPX; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TPX; ++j) acc[(i * C::TPX + j) * kWave] = accP[i][j];
+#pragma unroll
+      for (int i = 0; i < C::TRX; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TPX; ++j) acc[(C::TPX * C::TPX + i * C::TPX + j) * kWave] = accR[i][j];
     }
     wave_sync();  // the staging buffer is rewritten by the next group
   }
+  if (eside) {
+    // one partial row per workgroup: [A (na x na) | B (mr x na)] column-major, then sum of
+    // res2; the four waves' values are added in wave order
+    const int nent = ena * ena + emr * ena;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) racc += __shfl_xor(racc, o, kWave);
+    if (lane == 0) sRacc[wv] = racc;
+    __syncthreads();  // every wave is done with its staging area
+    float* red = sY[0];  // kFastWaves x nent, spans the staging areas
+    const int col = lane % 16;
+#pragma unroll
+    for (int i = 0; i < C::TPX; ++i)
+#pragma unroll
+      for (int j = 0; j < C::TPX; ++j) {
+        const f32x4 v4 = acc[(i * C::TPX + j) * kWave];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * i + 4 * (lane / 16) + v, c = 16 * j + col;
+          if (r < ena && c < ena) red[wv * nent + r + ena * c] = v4[v];
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < C::TRX; ++i)
+#pragma unroll
+      for (int j = 0; j < C::TPX; ++j) {
+        const f32x4 v4 = acc[(C::TPX * C::TPX + i * C::TPX + j) * kWave];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * i + 4 * (lane / 16) + v, c = 16 * j + col;
+          if (r < emr && c < ena) red[wv * nent + ena * ena + r + emr * c] = v4[v];
+        }
+      }
+    __syncthreads();
+    double* row = a.sums_part + (size_t)blockIdx.x * (nent + 1);
+    for (int e = tid; e < nent; e += blockDim.x) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < kFastWaves; ++q) v += (double)red[q * nent + e];
+      row[e] = v;
+    }
+    if (tid == 0) row[nent] = ((sRacc[0] + sRacc[1]) + sRacc[2]) + sRacc[3];
+  }
+}
+
+int g_num_cus = 256;
+
+// persistent grid: one workgroup per SIMD slot the variant's register budget allows
+int64_t fast_blocks(int64_t N, int spw, int wpe) {
+  const int64_t ngroups = (N + spw - 1) / spw;
+  int64_t blocks = (ngroups + kFastWaves - 1) / kFastWaves;
+  const int64_t cap = (int64_t)g_num_cus * (wpe > 1 ? wpe : 1);
+  if (blocks > cap) blocks = cap;
+  if (blocks > kFastMaxBlocks) blocks = kFastMaxBlocks;
+  if (blocks < 1) blocks = 1;
+  return blocks;
 }
 
 template <class C>
 hipError_t launch_cfg(const OmpArgs<float>& a, hipStream_t st) {
-  const int64_t ngroups = (a.N + C::SPW - 1) / C::SPW;
-  int64_t blocks = (ngroups + kFastWaves - 1) / kFastWaves;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
+  const int64_t blocks = fast_blocks(a.N, C::SPW, C::WPE);
   hipLaunchKernelGGL(omp_fast_kernel<C>, dim3((unsigned)blocks), dim3(kWave * kFastWaves), 0, st, a);
   return hipGetLastError();
 }
@@ -358,6 +502,22 @@ bool omp_fast_supported<float>(int m1, int m2, int n1, int n2, int s) {
 template <>
 bool omp_fast_supported<double>(int, int, int, int, int) {
   return false;
+}
+
+int omp_fast_partial_rows(int64_t N, int m1, int m2, int n1, int n2, int s) {
+  const int id = omp_fast_choice(m1, m2, n1, n2, s);
+  if (id < 0) return 0;
+  return (int)fast_blocks(N, 64 / (kVariants[id].lr * kVariants[id].lc), kVariants[id].wpe);
+}
+
+int omp_fast_max_partial_rows() { return kFastMaxBlocks; }
+
+hipError_t omp_fast_init_device() {
+  int dev = 0, n = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess && n > 0) g_num_cus = n;
+  return e;
 }
 
 int omp_fast_variants(int m1, int m2, int n1, int n2, int s, int* ids, int cap) {

@@ -59,6 +59,7 @@ int get_ctx(hipStream_t st, Ctx** out) {
     c->device = dev;
     hipError_t e = omp_generic_init_device();
     if (e == hipSuccess) e = tmod_sums_init_device();
+    if (e == hipSuccess) e = omp_fast_init_device();
     if (e != hipSuccess) {
       delete c;
       return fail(SDL_E_DEVICE, "kernel attribute setup: %s", hipGetErrorString(e));
@@ -164,8 +165,9 @@ struct PBuf {
   double* G2_64;
   void* G1c;
   void* G2c;
-  double* part;
-  double* sums;
+  double* part;   // workgroup / wave partial rows of the TMOD sums
+  double* stage;  // first-stage reduction rows
+  double* sums;   // reduced [A | B | sum res2]
   double* w;
   double* rpart;
   int nblk, rblk, nent;
@@ -201,9 +203,11 @@ void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Pla
     x.nent = na * na + mr * na;
     const int nb1 = tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2), nb2 = tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1);
     x.nblk = nb1 > nb2 ? nb1 : nb2;
+    const int rows = x.nblk > omp_fast_max_partial_rows() ? x.nblk : omp_fast_max_partial_rows();
     x.rblk = rmse_num_blocks(r.N);
-    x.part = b.take<double>((size_t)x.nblk * x.nent);
-    x.sums = b.take<double>((size_t)x.nent);
+    x.part = b.take<double>((size_t)rows * (x.nent + 1));
+    x.stage = b.take<double>((size_t)reduce_stage_rows(rows) * (x.nent + 1));
+    x.sums = b.take<double>((size_t)x.nent + 1);
     x.w = b.take<double>((size_t)na);
     x.rpart = b.take<double>((size_t)x.rblk);
   }
@@ -262,14 +266,24 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
   a.dep_eps = o.dep_eps;
   a.pivot_fp64 = o.pivot_fp64;
   a.counters = pl.counters;
+  a.sums_side = 0;
+  a.sums_part = nullptr;
   return a;
 }
 
 template <typename T>
-int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, T* res2_override, Launcher& L) {
+bool use_fast(const sdl_problem& r, const Opt& o) {
+  return o.kernel != 1 && omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s);
+}
+
+// sums_side != 0 (register-resident path only): the sweep also writes the partial
+// rows of that side's TMOD sums and of sum(res2) into b.part.
+template <typename T>
+int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, int sums_side, Launcher& L) {
   OmpArgs<T> a = omp_args<T>(r, b, o, pl);
-  if (res2_override) a.res2 = res2_override;
-  const bool fast = o.kernel != 1 && omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s);
+  a.sums_side = sums_side;
+  a.sums_part = b.part;
+  const bool fast = use_fast<T>(r, o);
   if (o.kernel == 2 && !fast)
     return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for m=%dx%d n=%dx%d s=%d in this precision", r.m1,
                 r.m2, r.n1, r.n2, r.s);
@@ -286,7 +300,29 @@ int run_prep(const sdl_problem& r, const PBuf& b, Launcher& L) {
   return L.end();
 }
 
-// one TMOD half-step: sums -> reduce -> solve (+ optional rescale of coef)
+// reduce the partial rows of one side's sums (plus the res2 entry when fused) and solve;
+// rmse_q >= 0: also record the RMSE of the sweep that produced the codes for problem rmse_q
+template <typename T>
+int run_reduce_solve(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, int rows, bool with_res2,
+                     int rmse_q, int K, Launcher& L) {
+  const int na = side == 1 ? r.n1 : r.n2, mr = side == 1 ? r.m1 : r.m2;
+  const int nent = na * na + mr * na;
+  SDL_TRY(L.begin(2));
+  HIP_TRY(launch_reduce_partials(b.part, rows, nent + (with_res2 ? 1 : 0), b.stage, b.sums, L.st));
+  SDL_TRY(L.end());
+  RmseOut ro{nullptr, nullptr, 0, 0, 0.0};
+  if (rmse_q >= 0) ro = RmseOut{pl.trace, pl.iter + rmse_q, rmse_q * (K + 1), nent, (double)r.N * r.m1 * r.m2};
+  SDL_TRY(L.begin(3));
+  if (side == 1)
+    HIP_TRY(launch_tmod_solve<T>(b.sums, r.m1, r.n1, r.D1, (T*)b.Dc1, b.G1_64, (T*)b.G1c, b.w, pl.status,
+                                 pl.counters, ro, L.st));
+  else
+    HIP_TRY(launch_tmod_solve<T>(b.sums, r.m2, r.n2, r.D2, (T*)b.Dc2, b.G2_64, (T*)b.G2c, b.w, pl.status,
+                                 pl.counters, ro, L.st));
+  return L.end();
+}
+
+// one TMOD half-step from the codes in supp/coef: standalone sums -> reduce -> solve (+ rescale)
 template <typename T>
 int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bool rescale, Launcher& L) {
   TmodArgs<T> a;
@@ -296,23 +332,11 @@ int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bo
   a.Dother = (const T*)(side == 1 ? b.Dc2 : b.Dc1);
   a.supp = r.supp;
   a.coef = (const T*)r.coef;
-  const int na = side == 1 ? r.n1 : r.n2, mr = side == 1 ? r.m1 : r.m2;
-  const int nent = na * na + mr * na;
-  SDL_TRY(L.begin(1));
   const int nblk = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2) : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1);
-  HIP_TRY(launch_tmod_sums<T>(a, b.part, nblk, L.st));
+  SDL_TRY(L.begin(1));
+  HIP_TRY(launch_tmod_sums<T>(a, b.part, L.st));
   SDL_TRY(L.end());
-  SDL_TRY(L.begin(2));
-  HIP_TRY(launch_reduce_partials(b.part, nblk, nent, b.sums, L.st));
-  SDL_TRY(L.end());
-  SDL_TRY(L.begin(3));
-  if (side == 1)
-    HIP_TRY(launch_tmod_solve<T>(b.sums, r.m1, r.n1, r.D1, (T*)b.Dc1, b.G1_64, (T*)b.G1c, b.w, pl.status,
-                                 pl.counters, L.st));
-  else
-    HIP_TRY(launch_tmod_solve<T>(b.sums, r.m2, r.n2, r.D2, (T*)b.Dc2, b.G2_64, (T*)b.G2c, b.w, pl.status,
-                                 pl.counters, L.st));
-  SDL_TRY(L.end());
+  SDL_TRY(run_reduce_solve<T>(side, r, b, pl, nblk, false, -1, 0, L));
   if (rescale) {
     SDL_TRY(L.begin(6));
     HIP_TRY(launch_rescale<T>(side, r.n1, r.s, r.N, r.supp, (T*)r.coef, b.w, L.st));
@@ -392,7 +416,7 @@ int sparse_code_impl(const sdl_problem* p, int nprob, const Opt& o, hipStream_t 
   for (int q = 0; q < nprob; ++q) {
     if (p[q].N == 0) continue;
     SDL_TRY(run_prep<T>(p[q], pl.pb[q], L));
-    SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, nullptr, L));
+    SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, 0, L));
   }
   return finish_call(st, ctx, pl, o, marks, false);
 }
@@ -426,15 +450,24 @@ int one_iteration(sdl_problem* p, int nprob, int K, const Opt& o, const Plan& pl
     const sdl_problem& r = p[q];
     if (r.N == 0) continue;
     const PBuf& b = pl.pb[q];
-    SDL_TRY(run_omp<T>(r, b, o, pl, nullptr, L));
-    SDL_TRY(run_rmse<T>(r, b, pl, q, K, L));
-    if (o.schedule == 0) {
-      SDL_TRY(run_update<T>(1, r, b, pl, false, L));
-      SDL_TRY(run_omp<T>(r, b, o, pl, nullptr, L));
-      SDL_TRY(run_update<T>(2, r, b, pl, false, L));
+    if (o.schedule == 0 && use_fast<T>(r, o)) {
+      // Algorithm 1 with the sums (and the RMSE) computed in the sparse-coding epilogue
+      const int rows = omp_fast_partial_rows(r.N, r.m1, r.m2, r.n1, r.n2, r.s);
+      SDL_TRY(run_omp<T>(r, b, o, pl, 1, L));
+      SDL_TRY(run_reduce_solve<T>(1, r, b, pl, rows, true, q, K, L));
+      SDL_TRY(run_omp<T>(r, b, o, pl, 2, L));
+      SDL_TRY(run_reduce_solve<T>(2, r, b, pl, rows, true, -1, K, L));
     } else {
-      SDL_TRY(run_update<T>(2, r, b, pl, true, L));
-      SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+      SDL_TRY(run_omp<T>(r, b, o, pl, 0, L));
+      SDL_TRY(run_rmse<T>(r, b, pl, q, K, L));
+      if (o.schedule == 0) {
+        SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+        SDL_TRY(run_omp<T>(r, b, o, pl, 0, L));
+        SDL_TRY(run_update<T>(2, r, b, pl, false, L));
+      } else {
+        SDL_TRY(run_update<T>(2, r, b, pl, true, L));
+        SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+      }
     }
   }
   return SDL_OK;
@@ -492,7 +525,7 @@ int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hi
   }
   for (int q = 0; q < nprob; ++q) {
     if (p[q].N == 0) continue;
-    SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, nullptr, L));
+    SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, 0, L));
     SDL_TRY(run_rmse<T>(p[q], pl.pb[q], pl, q, K, L));
   }
   int rc = finish_call(st, ctx, pl, o, marks, true);

@@ -32,6 +32,11 @@ struct OmpArgs {
   T* res2;  // may be null
   double stop_rel, dep_eps, pivot_fp64;
   unsigned long long* counters;  // kNumCounters entries
+  // Register-resident kernel only: also accumulate the TMOD sums of the new codes for
+  // side sums_side (1: D1 update, 2: D2 update; 0: none) plus the sum of res2, one
+  // row of (nent + 1) doubles per wave into sums_part (see omp_fast_partial_rows).
+  int sums_side;
+  double* sums_part;
 };
 
 // Buffers describing one TMOD half-step for one problem.
@@ -59,23 +64,38 @@ void omp_fast_variant_info(int id, int* lr, int* lc, int* wpe);
 hipError_t launch_omp_fast_variant(int id, const OmpArgs<float>& a, hipStream_t st);
 // Variant used for a shape: the autotuned one if tuned in this process, else the first listed.
 int omp_fast_choice(int m1, int m2, int n1, int n2, int s);
+// Partial rows (workgroups) of a register-resident launch over N signals with the
+// variant currently chosen for the shape, and the maximum over all variants.
+int omp_fast_partial_rows(int64_t N, int m1, int m2, int n1, int n2, int s);
+int omp_fast_max_partial_rows();
+hipError_t omp_fast_init_device();
 void omp_fast_set_choice(int m1, int m2, int n1, int n2, int s, int id);
 hipError_t autotune_problem(const OmpArgs<float>& a, hipStream_t st, int reps, int* chosen, double* best_ms);
 bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* wpe, double* ms);
 size_t omp_generic_lds_bytes(int m1, int m2, int n1, int n2, int s, size_t elem);
 hipError_t omp_generic_init_device();
 
-// Number of workgroup partials of the sums kernel (a fixed function of N and the shape).
+// Workgroup partials of the standalone sums kernel (a fixed function of N and the shape).
 int tmod_num_blocks_for(int64_t N, int na, int mr, int mc);
 hipError_t tmod_sums_init_device();
 template <typename T>
-hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, int nblk, hipStream_t st);
-hipError_t launch_reduce_partials(const double* part, int nblk, int nent, double* out, hipStream_t st);
-// Solve + normalise. D: the dictionary being updated (mr x na FP64, in/out).
-// Writes D (unless singular), Dc (compute-type copy), G64, Gc, w; ORs status; counts unused atoms.
+hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, hipStream_t st);
+// out[e] = sum_b part[b][e] in a fixed order (two stages when P > 64; stage holds
+// reduce_stage_rows(P) x nent doubles).
+hipError_t launch_reduce_partials(const double* part, int P, int nent, double* stage, double* out, hipStream_t st);
+int reduce_stage_rows(int P);
+// Optional RMSE output of the solve kernel: trace[*counter + offset] = sqrt(sums[idx] / denom), then ++*counter.
+struct RmseOut {
+  double* trace;  // null: no RMSE
+  int* counter;
+  int offset;
+  int idx;
+  double denom;
+};
+// Solve + normalise (one wavefront). D: the dictionary being updated (mr x na FP64, in/out).
 template <typename T>
-hipError_t launch_tmod_solve(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc,
-                             double* w, int* status, unsigned long long* counters, hipStream_t st);
+hipError_t launch_tmod_solve(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
+                             int* status, unsigned long long* counters, const RmseOut& r, hipStream_t st);
 template <typename T>
 hipError_t launch_dict_prep(const double* D, int mr, int na, T* Dc, double* G64, T* Gc, hipStream_t st);
 template <typename T>

@@ -16,149 +16,54 @@
 #include <math.h>
 
 #include "sdl_internal.h"
+#include "tmod_device.h"
 
 namespace sdl {
 namespace {
 
-// out[e] = sum over workgroup partials b of part[b][e], in a fixed order: four
-// interleaved stripes per entry, then the stripes in order.
-__global__ void __launch_bounds__(256) reduce_partials_kernel(const double* __restrict__ part, int nblk, int nent,
-                                                              double* out) {
-  __shared__ double red[4][64];
-  const int el = threadIdx.x % 64, stripe = threadIdx.x / 64;
-  const int e = blockIdx.x * 64 + el;
+// Fixed-order two-stage reduction of P partial rows of nent doubles: stage 1 sums
+// consecutive chunks of kChunk rows per entry (in row order), stage 2 the chunk sums
+// (in chunk order).
+constexpr int kChunk = 64;
+
+__global__ void reduce_stage1_kernel(const double* __restrict__ part, int P, int nent, double* stage) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (e >= nent) return;
+  const int b1 = (c + 1) * kChunk < P ? (c + 1) * kChunk : P;
   double v = 0.0;
-  if (e < nent) {
-#pragma unroll 8
-    for (int b = stripe; b < nblk; b += 4) v += part[(size_t)b * nent + e];
-  }
-  red[stripe][el] = v;
-  __syncthreads();
-  if (stripe == 0 && e < nent) out[e] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
+#pragma unroll 16
+  for (int b = c * kChunk; b < b1; ++b) v += part[(size_t)b * nent + e];
+  stage[(size_t)c * nent + e] = v;
 }
 
-// D (mr x na FP64) -> compute-type copy, FP64 and compute-type Gram D^T D.
+__global__ void reduce_stage2_kernel(const double* __restrict__ stage, int nchunk, int nent, double* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nent) return;
+  double v = 0.0;
+  for (int c = 0; c < nchunk; ++c) v += stage[(size_t)c * nent + e];
+  out[e] = v;
+}
+
+// Solve + normalise on one wavefront; optionally turn the reduced sum of squared
+// residuals (sums[r.idx]) into the RMSE of the sweep that produced the codes.
 template <typename T>
-__device__ void write_copies(const double* D, int mr, int na, T* Dc, double* G64, T* Gc) {
-  for (int e = threadIdx.x; e < mr * na; e += blockDim.x) Dc[e] = (T)D[e];
-  for (int e = threadIdx.x; e < na * na; e += blockDim.x) {
-    const int i = e % na, j = e / na;
-    double v = 0.0;
-    for (int p = 0; p < mr; ++p) v += D[p + mr * i] * D[p + mr * j];
-    G64[e] = v;
-    Gc[e] = (T)v;
+__global__ void __launch_bounds__(kWave)
+    tmod_solve_kernel(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
+                      int* status, unsigned long long* counters, RmseOut r) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x;
+  if (r.trace && lane == 0) {
+    const int it = *r.counter;
+    r.trace[(size_t)it + r.offset] = r.denom > 0 ? sqrt(sums[r.idx] / r.denom) : 0.0;
+    *r.counter = it + 1;
   }
+  solve_update<T>(sums, mr, na, D, Dc, G64, Gc, w, status, counters, smem_raw, lane);
 }
 
 template <typename T>
 __global__ void dict_prep_kernel(const double* D, int mr, int na, T* Dc, double* G64, T* Gc) {
-  write_copies<T>(D, mr, na, Dc, G64, Gc);
-}
-
-constexpr double kSpdRelTol = 1e-12;  // pivot <= tol * diagonal entry -> not positive definite
-constexpr int kLd = SDL_MAX_N + 1;     // padded LDS row length
-
-__device__ inline void wsync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// One wavefront: FP64 Cholesky of the Gram sum on the used atoms, two triangular
-// solves with mr right-hand sides, normalisation.  sums = [A (na x na) | B (mr x na)],
-// column-major.  All steps are wave-synchronous (no workgroup barriers).
-template <typename T>
-__global__ void __launch_bounds__(64)
-    tmod_solve_kernel(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
-                      int* status, unsigned long long* counters) {
-  __shared__ double C[SDL_MAX_N * kLd];
-  __shared__ double X[SDL_MAX_N * kLd];  // X[k][p]: right-hand sides / solution, atom k, row p
-  __shared__ double diag0[SDL_MAX_N];
-  __shared__ int U[SDL_MAX_N];
-  const int lane = threadIdx.x;
-  const double* A = sums;
-  const double* B = sums + na * na;
-  // used atoms (positive diagonal), compacted in index order with a ballot
-  const bool used = lane < na && A[lane + na * lane] > 0.0;
-  const unsigned long long mask = __ballot(used);
-  const int nu = __popcll(mask);
-  if (used) U[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
-  if (lane == 0 && nu < na) atomicAdd(&counters[kCtrUnusedAtoms], (unsigned long long)(na - nu));
-  wsync();
-  for (int e = lane; e < nu * nu; e += 64) {
-    const int k = e % nu, l = e / nu;
-    C[k * kLd + l] = A[U[k] + na * U[l]];
-    if (k == l) diag0[k] = C[k * kLd + k];
-  }
-  for (int e = lane; e < nu * mr; e += 64) {
-    const int k = e % nu, p = e / nu;
-    X[k * kLd + p] = B[p + mr * U[k]];
-  }
-  wsync();
-  bool bad = false;
-  for (int k = 0; k < nu && !bad; ++k) {
-    const double d = C[k * kLd + k];
-    if (!(d > kSpdRelTol * diag0[k])) {
-      bad = true;
-      break;
-    }
-    const double lkk = sqrt(d), inv = 1.0 / lkk;
-    wsync();
-    if (lane == 0) C[k * kLd + k] = lkk;
-    for (int i = k + 1 + lane; i < nu; i += 64) C[i * kLd + k] *= inv;
-    wsync();
-    const int rem = nu - k - 1;
-    for (int e = lane; e < rem * rem; e += 64) {
-      const int i = k + 1 + e % rem, j = k + 1 + e / rem;
-      if (j <= i) C[i * kLd + j] -= C[i * kLd + k] * C[j * kLd + k];
-    }
-    wsync();
-  }
-  if (!bad) {
-    // L Z = X (forward), then L^T X = Z (backward); columns p in parallel
-    for (int k = 0; k < nu; ++k) {
-      const double inv = 1.0 / C[k * kLd + k];
-      for (int p = lane; p < mr; p += 64) X[k * kLd + p] *= inv;
-      wsync();
-      for (int e = lane; e < (nu - k - 1) * mr; e += 64) {
-        const int i = k + 1 + e / mr, p = e % mr;
-        X[i * kLd + p] -= C[i * kLd + k] * X[k * kLd + p];
-      }
-      wsync();
-    }
-    for (int k = nu - 1; k >= 0; --k) {
-      const double inv = 1.0 / C[k * kLd + k];
-      for (int p = lane; p < mr; p += 64) X[k * kLd + p] *= inv;
-      wsync();
-      for (int e = lane; e < k * mr; e += 64) {
-        const int i = e / mr, p = e % mr;
-        X[i * kLd + p] -= C[k * kLd + i] * X[k * kLd + p];
-      }
-      wsync();
-    }
-    // normalisation W: unit-norm columns; a zero column keeps the old atom; unused atoms kept
-    for (int i = lane; i < na; i += 64) w[i] = 1.0;
-    wsync();
-    for (int k = lane; k < nu; k += 64) {
-      const int i = U[k];
-      double nrm = 0.0;
-      for (int p = 0; p < mr; ++p) nrm += X[k * kLd + p] * X[k * kLd + p];
-      nrm = sqrt(nrm);
-      if (nrm > 0.0) {
-        w[i] = nrm;
-        for (int p = 0; p < mr; ++p) D[p + mr * i] = X[k * kLd + p] / nrm;
-      }
-    }
-  } else {
-    for (int i = lane; i < na; i += 64) w[i] = 1.0;
-    if (lane == 0) {
-      atomicOr(status, kStatusSingular);
-      atomicAdd(&counters[kCtrSingular], 1ull);
-    }
-  }
-  __threadfence_block();
-  wsync();
-  write_copies<T>(D, mr, na, Dc, G64, Gc);
+  write_copies<T>(D, mr, na, Dc, G64, Gc, threadIdx.x, blockDim.x);
 }
 
 template <typename T>
@@ -216,16 +121,26 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
 
 }  // namespace
 
-hipError_t launch_reduce_partials(const double* part, int nblk, int nent, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nent + 63) / 64), dim3(256), 0, st, part, nblk, nent, out);
+hipError_t launch_reduce_partials(const double* part, int P, int nent, double* stage, double* out,
+                                 hipStream_t st) {
+  const int nchunk = (P + kChunk - 1) / kChunk;
+  const dim3 g1((nent + 255) / 256, nchunk);
+  if (nchunk == 1) {
+    hipLaunchKernelGGL(reduce_stage1_kernel, g1, dim3(256), 0, st, part, P, nent, out);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(reduce_stage1_kernel, g1, dim3(256), 0, st, part, P, nent, stage);
+  hipLaunchKernelGGL(reduce_stage2_kernel, dim3((nent + 255) / 256), dim3(256), 0, st, stage, nchunk, nent, out);
   return hipGetLastError();
 }
 
+int reduce_stage_rows(int P) { return (P + kChunk - 1) / kChunk; }
+
 template <typename T>
 hipError_t launch_tmod_solve(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
-                             int* status, unsigned long long* counters, hipStream_t st) {
-  hipLaunchKernelGGL(tmod_solve_kernel<T>, dim3(1), dim3(64), 0, st, sums, mr, na, D, Dc, G64, Gc, w,
-                     status, counters);
+                             int* status, unsigned long long* counters, const RmseOut& r, hipStream_t st) {
+  hipLaunchKernelGGL(tmod_solve_kernel<T>, dim3(1), dim3(kWave), solve_lds_bytes(na, mr), st, sums, mr, na, D, Dc,
+                     G64, Gc, w, status, counters, r);
   return hipGetLastError();
 }
 
@@ -276,7 +191,7 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st) {
 
 #define SDL_INST(T)                                                                                            \
   template hipError_t launch_tmod_solve<T>(const double*, int, int, double*, T*, double*, T*, double*, int*,  \
-                                           unsigned long long*, hipStream_t);                                 \
+                                           unsigned long long*, const RmseOut&, hipStream_t);                 \
   template hipError_t launch_dict_prep<T>(const double*, int, int, T*, double*, T*, hipStream_t);             \
   template hipError_t launch_rescale<T>(int, int, int, int64_t, const int32_t*, T*, const double*,            \
                                         hipStream_t);                                                         \

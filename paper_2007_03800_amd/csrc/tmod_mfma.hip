@@ -10,14 +10,17 @@
 // LDS from the sparse codes (one lane per column, so the scatter has no
 // conflicts), stages Ycat with coalesced loads, and runs 16x16x4 MFMAs with FP32
 // (or FP64) accumulation over K.  The four waves of a workgroup add their tiles in
-// a fixed order and write one FP64 partial per workgroup; no atomics anywhere, so
-// results are bitwise reproducible.
+// a fixed order and write one FP64 partial per workgroup; a separate fixed-order
+// reduction and the FP64 solve follow (no floating-point atomics anywhere, so
+// results are bitwise reproducible).
 #include "sdl_internal.h"
 
 namespace sdl {
 namespace {
 
 constexpr int kWaves = 4;
+constexpr int kMaxBlocks = 512;
+constexpr int kMaxDynLds = 160 * 1024;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -48,7 +51,7 @@ __device__ inline void wave_sync() {
 
 // TP = 16-row tiles over the na atoms, TR = 16-row tiles over the mr signal rows.
 template <typename T, int TP, int TR>
-__global__ void __launch_bounds__(kWave* kWaves) tmod_sums_mfma_kernel(TmodArgs<T> a, double* part, int nblk, int bs) {
+__global__ void __launch_bounds__(kWave* kWaves) tmod_sums_kernel(TmodArgs<T> a, double* part, int nblk, int bs) {
   using MF = Mfma<T>;
   using V = typename MF::V;
   constexpr int NP = 16 * TP + 1, MP = 16 * TR + 1;  // padded LDS row lengths (bank spread)
@@ -61,8 +64,15 @@ __global__ void __launch_bounds__(kWave* kWaves) tmod_sums_mfma_kernel(TmodArgs<
   const int M = a.m1 * a.m2;
   const int K = bs * mc, K4 = (K + 3) & ~3;
   const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-  T* Tb = smem + (size_t)w * K4 * (NP + MP);  // [K4][NP]
-  T* Yt = Tb + (size_t)K4 * NP;                // [K4][MP]
+  const int nbo = side == 1 ? a.n2 : a.n1;                 // atoms of the fixed dictionary
+  const size_t per_wave = (size_t)K4 * (NP + MP) + 2 * (size_t)bs * s;
+  T* Do = smem + (size_t)kWaves * per_wave;                // fixed dictionary, mc x nbo
+  T* Tb = smem + (size_t)w * per_wave;                     // [K4][NP]  Tcat, column-major by k
+  T* Yt = Tb + (size_t)K4 * NP;                            // [K4][MP]  Ycat
+  T* cval = Yt + (size_t)K4 * MP;                          // codes of the batch
+  int* cidx = reinterpret_cast<int*>(cval + bs * s);
+  for (int e = tid; e < mc * nbo; e += blockDim.x) Do[e] = a.Dother[e];
+  __syncthreads();
   const int64_t k0 = (a.N * blockIdx.x) / nblk, k1 = (a.N * (blockIdx.x + 1)) / nblk;
   const int64_t nbatch = (k1 - k0 + bs - 1) / bs;
 
@@ -79,27 +89,35 @@ __global__ void __launch_bounds__(kWave* kWaves) tmod_sums_mfma_kernel(TmodArgs<
   for (int64_t bi = w; bi < nbatch; bi += kWaves) {
     const int64_t kb = k0 + bi * bs;
     const int nb = (int)((k1 - kb) < bs ? (k1 - kb) : bs);
-    for (int e = lane; e < K4 * NP; e += kWave) Tb[e] = T(0);
-    for (int e = lane; e < K4 * MP; e += kWave) Yt[e] = T(0);
-    wave_sync();
-    // Ycat: column (b*mc + c), row r holds Yt_b[r][c]; global reads are contiguous
-    for (int e = lane; e < nb * M; e += kWave) {
-      const int b = e / M, pix = e % M;
-      const int p = pix % a.m1, q = pix / a.m1;  // Y_b[p, q]
-      const int r = side == 1 ? p : q, c = side == 1 ? q : p;
-      Yt[(b * mc + c) * MP + r] = a.Y[(kb + b) * M + pix];
+    // the batch's codes, staged with contiguous loads
+    for (int e = lane; e < nb * s; e += kWave) {
+      cidx[e] = a.supp[kb * s + e];
+      cval[e] = a.coef[kb * s + e];
     }
-    // Tcat: lane per column (b, c): T_b[ra][c] += x * Do[c, rb] over the code of signal b
-    for (int e = lane; e < nb * mc; e += kWave) {
+    wave_sync();
+    // each lane owns whole columns k = b*mc + c of Tcat and Ycat: no cross-lane hazards
+    for (int e = lane; e < K4; e += kWave) {
       const int b = e / mc, c = e % mc;
-      const int64_t k = kb + b;
-      T* col = Tb + (size_t)(b * mc + c) * NP;
-      for (int t = 0; t < s; ++t) {
-        const int at = a.supp[k * s + t];
-        if (at < 0) continue;
-        const int i = at % n1, j = at / n1;
-        const int ra = side == 1 ? i : j, rb = side == 1 ? j : i;
-        col[ra] += a.coef[k * s + t] * a.Dother[c + mc * rb];
+      T* tcol = Tb + (size_t)e * NP;
+      T* ycol = Yt + (size_t)e * MP;
+      for (int r = 0; r < NP; ++r) tcol[r] = T(0);
+      if (b < nb) {
+        for (int t = 0; t < s; ++t) {
+          const int at = cidx[b * s + t];
+          if (at < 0) continue;
+          const int i = at % n1, j = at / n1;
+          const int ra = side == 1 ? i : j, rb = side == 1 ? j : i;
+          tcol[ra] += cval[b * s + t] * Do[c + mc * rb];
+        }
+        const T* Yb = a.Y + (kb + b) * M;
+        if (side == 1) {
+          for (int r = 0; r < mr; ++r) ycol[r] = Yb[r + a.m1 * c];  // column c of Y_b
+        } else {
+          for (int r = 0; r < mr; ++r) ycol[r] = Yb[c + a.m1 * r];  // row c of Y_b
+        }
+        for (int r = mr; r < MP; ++r) ycol[r] = T(0);
+      } else {
+        for (int r = 0; r < MP; ++r) ycol[r] = T(0);
       }
     }
     wave_sync();
@@ -159,7 +177,7 @@ __global__ void __launch_bounds__(kWave* kWaves) tmod_sums_mfma_kernel(TmodArgs<
 
 template <typename T, int TP, int TR>
 hipError_t launch_tp_tr(const TmodArgs<T>& a, double* part, int nblk, int bs, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((tmod_sums_mfma_kernel<T, TP, TR>), dim3(nblk), dim3(kWave * kWaves), lds, st, a, part, nblk, bs);
+  hipLaunchKernelGGL((tmod_sums_kernel<T, TP, TR>), dim3(nblk), dim3(kWave * kWaves), lds, st, a, part, nblk, bs);
   return hipGetLastError();
 }
 
@@ -188,20 +206,25 @@ static int sums_batch(int na, int mr, int mc) {
 int tmod_num_blocks_for(int64_t N, int na, int mr, int mc) {
   const int bs = sums_batch(na, mr, mc);
   int64_t b = (N + (int64_t)kWaves * bs - 1) / ((int64_t)kWaves * bs);
-  if (b > 512) b = 512;
+  if (b > kMaxBlocks) b = kMaxBlocks;
   if (b < 1) b = 1;
   return (int)b;
 }
 
+
+
 template <typename T>
-hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, int nblk, hipStream_t st) {
+hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, hipStream_t st) {
   const int na = a.side == 1 ? a.n1 : a.n2;
   const int mr = a.side == 1 ? a.m1 : a.m2;
   const int mc = a.side == 1 ? a.m2 : a.m1;
   const int bs = sums_batch(na, mr, mc);
+  const int nblk = tmod_num_blocks_for(a.N, na, mr, mc);
   const int tp = (na + 15) / 16, tr = (mr + 15) / 16;
   const int K4 = (bs * mc + 3) & ~3;
-  size_t lds = (size_t)kWaves * K4 * (16 * tp + 1 + 16 * tr + 1) * sizeof(T);
+  const int mco = a.side == 1 ? a.n2 : a.n1;
+  size_t lds = ((size_t)kWaves * ((size_t)K4 * (16 * tp + 1 + 16 * tr + 1) + 2 * (size_t)bs * a.s) +
+                (size_t)mc * mco) * sizeof(T);
   const size_t red = (size_t)kWaves * (na * na + mr * na) * sizeof(T);
   if (red > lds) lds = red;
   switch (tp) {
@@ -214,8 +237,8 @@ hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, int nblk, hipStr
 
 template <typename T, int TP, int TR>
 hipError_t allow_lds() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&tmod_sums_mfma_kernel<T, TP, TR>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&tmod_sums_kernel<T, TP, TR>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
 }
 
 template <typename T>
@@ -234,7 +257,7 @@ hipError_t tmod_sums_init_device() {
   return e == hipSuccess ? allow_lds_all<double>() : e;
 }
 
-template hipError_t launch_tmod_sums<float>(const TmodArgs<float>&, double*, int, hipStream_t);
-template hipError_t launch_tmod_sums<double>(const TmodArgs<double>&, double*, int, hipStream_t);
+template hipError_t launch_tmod_sums<float>(const TmodArgs<float>&, double*, hipStream_t);
+template hipError_t launch_tmod_sums<double>(const TmodArgs<double>&, double*, hipStream_t);
 
 }  // namespace sdl
