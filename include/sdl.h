@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define SDL_ABI_VERSION 1
+#define SDL_ABI_VERSION 2
 
 typedef enum { SDL_FP64 = 0, SDL_FP32 = 1 } sdl_prec;
 
@@ -84,7 +84,12 @@ typedef struct sdl_stats {
    * reduction, 3 FP64 solve + normalise, 4 dictionary prep, 5 RMSE, 6 code rescale. */
   double kernel_ms[8];
   int64_t kernel_launches[8];
+  int64_t proposals_accepted; /* learned path: signals whose proposal passed the test */
+  int64_t fallbacks;          /* learned path: signals coded by the 2D-OMP fallback */
 } sdl_stats;
+
+/* Learned support proposal network (opaque; see sdl_proposer_* below). */
+typedef struct sdl_proposer sdl_proposer;
 
 typedef struct sdl_options {
   int32_t prec;             /* sdl_prec, default SDL_FP64 */
@@ -97,6 +102,8 @@ typedef struct sdl_options {
   double dep_eps;           /* OMP stops when the new Gram pivot <= dep_eps*G_aa; default 1e-10 */
   double pivot_fp64;        /* FP32: pivots below pivot_fp64*G_aa are recomputed in FP64; default 1e-3 */
   sdl_stats* stats;         /* host, optional */
+  sdl_proposer* proposer;   /* sdl_learn: code with the learned proposal + 2D-OMP fallback (NULL = plain) */
+  double tau;               /* acceptance threshold of the proposal: ||r||^2 <= tau*||Y||^2 (default 0) */
 } sdl_options;
 
 /* Fill *o with the defaults above (prec = SDL_FP64).  Passing NULL options to the
@@ -153,6 +160,47 @@ int sdl_kernel_variants(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t 
  * the autotuned or default one).  SDL_E_UNSUPPORTED if no such variant exists. */
 int sdl_set_kernel_variant(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t lanes_row,
                            int32_t lanes_col, int32_t waves_per_simd);
+
+/* ---- Learned support proposal (not part of the paper; an accelerator in front of 2D-OMP).
+ * An MLP maps vec(Y_k)/||Y_k||_F (m1*m2 inputs) through two GELU layers of `hidden` units to
+ * one logit per atom (n1*n2).  It is trained on the GPU by this library's own forward,
+ * backward and Adam kernels with mean sigmoid cross-entropy against the supports that
+ * 2D-OMP chose.  At inference the s largest logits (ties: smallest index) give the support,
+ * least squares on it gives the coefficients and the explicit residual; the proposal is
+ * accepted when ||r||^2 <= tau*||Y||^2, otherwise the signal is coded by 2D-OMP.
+ * Supported: m1*m2 = 64, n1*n2 in {144, 256}, hidden a multiple of 64, s <= 16, FP32
+ * signals; fp32_check = 1 runs the GEMMs in FP32 (for gradient checks), else BF16 with
+ * FP32 accumulation.  Weights: FP32 masters, flat layout [W1 (hidden x m1m2, row = unit),
+ * b1, W2 (hidden x hidden), b2, W3 (n1n2 x hidden), b3], seeded Kaiming-normal init.
+ * Device pointers: Y (N x m1*m2 floats, column-major signals), supp (N x s int32),
+ * logits (N x n1n2 floats), accept (N int32).  Calls are synchronous unless noted. */
+int sdl_proposer_create(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t hidden, int32_t fp32_check,
+                        uint64_t seed, sdl_proposer** out);
+void sdl_proposer_destroy(sdl_proposer* p);
+int64_t sdl_proposer_num_params(const sdl_proposer* p);
+int sdl_proposer_get_params(const sdl_proposer* p, float* host);      /* np floats */
+int sdl_proposer_set_params(sdl_proposer* p, const float* host);      /* also resets the Adam state */
+/* Mean BCE loss and its gradient (host, np floats) on B signals (B % 64 == 0), no update. */
+int sdl_proposer_gradient(sdl_proposer* p, const float* Y, const int32_t* supp, int32_t s, int64_t B,
+                          float* grad_host, double* loss_host, void* stream);
+/* Adam (lr, 0.9, 0.999, 1e-8) over `epochs` passes of floor(N/batch) shuffled batches;
+ * loss_trace (host, epochs, may be NULL) gets each epoch's mean batch loss. */
+int sdl_proposer_train(sdl_proposer* p, const float* Y, const int32_t* supp, int32_t s, int64_t N, int32_t epochs,
+                       int32_t batch, float lr, uint64_t seed, double* loss_trace, void* stream);
+/* Logits of N signals (asynchronous on stream). */
+int sdl_proposer_logits(sdl_proposer* p, const float* Y, int64_t N, float* logits, void* stream);
+/* Learned sparse coding of FP32 problems (options->tau is the acceptance threshold):
+ * proposal + least squares for every signal, register-resident 2D-OMP for the rejected
+ * ones.  accept (device, N int32, may be NULL; only with nprob == 1) receives 1 where the
+ * proposal was kept.  stats (if given) receives the accepted / fallback counts. */
+int sdl_learned_sparse_code(sdl_proposer* p, const sdl_problem* prob, int32_t nprob, int32_t* accept,
+                            const sdl_options* o, void* stream);
+/* Choose tau on a calibration problem: run the proposal (accepting everything) and plain
+ * 2D-OMP, sort signals by ||r_prop||^2/||Y||^2 and return the largest threshold such that at
+ * most `violation` of the accepted signals have ||r_prop||^2 > 1.01 * ||r_omp||^2.  The
+ * problem's codes are overwritten. */
+int sdl_proposer_calibrate(sdl_proposer* p, const sdl_problem* prob, double violation, double* tau_out,
+                           void* stream);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* sdl_last_error(void);

@@ -25,11 +25,13 @@ class Problem(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("early_stops", ctypes.c_int64), ("fp64_pivots", ctypes.c_int64), ("unused_atoms", ctypes.c_int64),
                 ("singular_updates", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 8),
-                ("kernel_launches", ctypes.c_int64 * 8)]
+                ("kernel_launches", ctypes.c_int64 * 8), ("proposals_accepted", ctypes.c_int64),
+                ("fallbacks", ctypes.c_int64)]
 
     def as_dict(self):
         return dict(early_stops=self.early_stops, fp64_pivots=self.fp64_pivots, unused_atoms=self.unused_atoms,
-                    singular_updates=self.singular_updates,
+                    singular_updates=self.singular_updates, proposals_accepted=self.proposals_accepted,
+                    fallbacks=self.fallbacks,
                     kernel_ms={KERNEL_CLASSES[i]: self.kernel_ms[i] for i in range(8) if self.kernel_launches[i]},
                     kernel_launches={KERNEL_CLASSES[i]: self.kernel_launches[i] for i in range(8)
                                      if self.kernel_launches[i]})
@@ -39,7 +41,7 @@ class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("schedule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("timing", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("stop_rel", ctypes.c_double), ("dep_eps", ctypes.c_double), ("pivot_fp64", ctypes.c_double),
-                ("stats", ctypes.POINTER(Stats))]
+                ("stats", ctypes.POINTER(Stats)), ("proposer", ctypes.c_void_p), ("tau", ctypes.c_double)]
 
 
 class SdlError(RuntimeError):
@@ -76,6 +78,23 @@ def lib():
         L.sdl_kernel_variants.restype = ctypes.c_int
         L.sdl_set_kernel_variant.argtypes = [ctypes.c_int32] * 8
         L.sdl_set_kernel_variant.restype = ctypes.c_int
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.sdl_proposer_create.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.sdl_proposer_destroy.argtypes = [vp]
+        L.sdl_proposer_destroy.restype = None
+        L.sdl_proposer_num_params.argtypes = [vp]
+        L.sdl_proposer_num_params.restype = i64
+        L.sdl_proposer_get_params.argtypes = [vp, vp]
+        L.sdl_proposer_set_params.argtypes = [vp, vp]
+        L.sdl_proposer_gradient.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp]
+        L.sdl_proposer_train.argtypes = [vp, vp, vp, i32, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, vp, vp]
+        L.sdl_proposer_logits.argtypes = [vp, vp, i64, vp, vp]
+        L.sdl_learned_sparse_code.argtypes = [vp, P, i32, vp, ctypes.POINTER(Options), vp]
+        L.sdl_proposer_calibrate.argtypes = [vp, P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+        for f in (L.sdl_proposer_create, L.sdl_proposer_get_params, L.sdl_proposer_set_params,
+                  L.sdl_proposer_gradient, L.sdl_proposer_train, L.sdl_proposer_logits, L.sdl_learned_sparse_code,
+                  L.sdl_proposer_calibrate):
+            f.restype = ctypes.c_int
         L.sdl_last_error.restype = ctypes.c_char_p
         L.sdl_last_error.argtypes = []
         L.sdl_abi_version.restype = ctypes.c_int

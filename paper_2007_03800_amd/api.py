@@ -124,11 +124,15 @@ def tmod_update(problems: Problem | Sequence[Problem], sides: int = 3, stream=No
     return problems
 
 
-def learn(problems: Problem | Sequence[Problem], K: int, stream=None, stats=None, **opts):
-    """Algorithm 1 for K iterations plus a final 2D-OMP.  Returns the RMSE trace (nprob, K+1)."""
+def learn(problems: Problem | Sequence[Problem], K: int, stream=None, stats=None, proposer=None, tau=0.0, **opts):
+    """Algorithm 1 for K iterations plus a final sparse coding.  Returns the RMSE trace (nprob, K+1).
+    With ``proposer`` every sparse coding uses the learned proposal with 2D-OMP fallback."""
     import numpy as np
     problems = [problems] if isinstance(problems, Problem) else list(problems)
     o = _options(problems, stats, **opts)
+    if proposer is not None:
+        o.proposer = proposer.handle
+        o.tau = tau
     arr = _array(problems)
     trace = np.zeros((max(1, len(problems)), K + 1), dtype=np.float64)
     st = _native.lib().sdl_learn(arr, len(problems), K, trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o),
@@ -165,6 +169,92 @@ def kernel_variants(m1, m2, n1, n2, s):
 
 def set_kernel_variant(m1, m2, n1, n2, s, variant):
     _native.check(_native.lib().sdl_set_kernel_variant(m1, m2, n1, n2, s, *variant))
+
+
+class Proposer:
+    """Learned support proposal network (see sdl_proposer_* in include/sdl.h).
+
+    Weights live on the device; ``params``/``set_params`` move the flat FP32 master
+    vector [W1 (hidden x m1m2), b1, W2, b2, W3 (n1n2 x hidden), b3]."""
+
+    def __init__(self, m1, m2, n1, n2, hidden=512, fp32_check=False, seed=7):
+        self._h = ctypes.c_void_p()
+        _native.check(_native.lib().sdl_proposer_create(m1, m2, n1, n2, hidden, int(bool(fp32_check)), seed,
+                                                        ctypes.byref(self._h)))
+        self.m1, self.m2, self.n1, self.n2, self.hidden = m1, m2, n1, n2, hidden
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        try:
+            if h is not None and h.value:
+                _native.lib().sdl_proposer_destroy(h)
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
+        self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def num_params(self):
+        return int(_native.lib().sdl_proposer_num_params(self._h))
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.num_params, np.float32)
+        _native.check(_native.lib().sdl_proposer_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.size == self.num_params
+        _native.check(_native.lib().sdl_proposer_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def gradient(self, Y: torch.Tensor, supp: torch.Tensor, s: int, stream=None):
+        """(mean BCE loss, flat FP32 gradient) on the B signals of Y (ABI layout, B % 64 == 0)."""
+        import numpy as np
+        g = np.empty(self.num_params, np.float32)
+        loss = ctypes.c_double()
+        _native.check(_native.lib().sdl_proposer_gradient(
+            self._h, ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(supp.data_ptr()), s, Y.shape[0],
+            g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss), _stream(stream)))
+        return loss.value, g
+
+    def train(self, Y: torch.Tensor, supp: torch.Tensor, s: int, epochs=5, batch=1024, lr=1e-3, seed=8, stream=None):
+        import numpy as np
+        tr = np.zeros(max(1, epochs))
+        _native.check(_native.lib().sdl_proposer_train(
+            self._h, ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(supp.data_ptr()), s, Y.shape[0], epochs, batch,
+            lr, seed, tr.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return tr[:epochs]
+
+    def logits(self, Y: torch.Tensor, stream=None):
+        out = torch.empty((Y.shape[0], self.n1 * self.n2), dtype=torch.float32, device=Y.device)
+        _native.check(_native.lib().sdl_proposer_logits(self._h, ctypes.c_void_p(Y.data_ptr()), Y.shape[0],
+                                                        ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def calibrate(self, problem: Problem, violation=0.01, stream=None):
+        tau = ctypes.c_double()
+        arr = _array([problem])
+        _native.check(_native.lib().sdl_proposer_calibrate(self._h, arr, violation, ctypes.byref(tau),
+                                                           _stream(stream)))
+        return tau.value
+
+
+def learned_sparse_code(proposer: Proposer, problems, tau: float, accept: torch.Tensor | None = None, stream=None,
+                        stats=None, **opts):
+    """Proposal + least squares, 2D-OMP for the rejected signals (FP32 problems)."""
+    problems = [problems] if isinstance(problems, Problem) else list(problems)
+    o = _options(problems, stats, **opts)
+    o.tau = tau
+    arr = _array(problems)
+    acc = ctypes.c_void_p(accept.data_ptr()) if accept is not None else None
+    _native.check(_native.lib().sdl_learned_sparse_code(proposer.handle, arr, len(problems), acc, ctypes.byref(o),
+                                                        _stream(stream)))
+    return problems
 
 
 def new_stats() -> _native.Stats:

@@ -119,7 +119,8 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
   const int lane_base = sr + N1 * sc;  // atom index of local element (ri, cj) = lane_base + LR*ri + N1*LC*cj
   const float stop_rel = (float)a.stop_rel, dep_eps = (float)a.dep_eps, piv = (float)a.pivot_fp64;
 
-  const int64_t ngroups = (a.N + SPW - 1) / SPW;
+  const int64_t nsig = a.index ? (int64_t)*a.count : a.N;  // signals to code
+  const int64_t ngroups = (nsig + SPW - 1) / SPW;
   float* ys = sY[wv];
   // epilogue accumulators (the next dictionary update's sums and sum of res2)
   const int eside = a.sums_side;
@@ -131,14 +132,25 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
   double racc = 0.0;
   for (int64_t grp = (int64_t)blockIdx.x * kFastWaves + wv; grp < ngroups; grp += (int64_t)gridDim.x * kFastWaves) {
     const int64_t k0 = grp * SPW;
-    const int nvalid = (int)((a.N - k0) < SPW ? (a.N - k0) : SPW);
-    // ---- stage the wave's signals (contiguous) through LDS, 16-byte chunks
+    const int nvalid = (int)((nsig - k0) < SPW ? (nsig - k0) : SPW);
+    // ---- stage the wave's signals through LDS, 16-byte chunks (contiguous, or gathered by index)
     {
-      const float4* src = reinterpret_cast<const float4*>(a.Y + k0 * M);
       float4* dst = reinterpret_cast<float4*>(ys);
       const int nchunk = nvalid * M / 4;
-      for (int e = lane; e < SPW * M / 4; e += kWave)
-        dst[e] = e < nchunk ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!a.index) {
+        const float4* src = reinterpret_cast<const float4*>(a.Y + k0 * M);
+        for (int e = lane; e < SPW * M / 4; e += kWave)
+          dst[e] = e < nchunk ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        for (int e = lane; e < SPW * M / 4; e += kWave) {
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (e < nchunk) {
+            const int b = e / (M / 4), off = e % (M / 4);
+            v = reinterpret_cast<const float4*>(a.Y + (int64_t)a.index[k0 + b] * M)[off];
+          }
+          dst[e] = v;
+        }
+      }
     }
     wave_sync();
     const float* y = ys + g * M;
@@ -330,7 +342,7 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
     }
     rr = group_sum<LG>(rr);
     if (valid) {
-      const int64_t k = k0 + g;
+      const int64_t k = a.index ? (int64_t)a.index[k0 + g] : k0 + g;
 #pragma unroll
       for (int t = 0; t < S; ++t) {
         if (t % LG == sub) {

@@ -10,9 +10,17 @@
 #include <utility>
 #include <vector>
 
+#include "mlp_internal.h"
 #include "sdl_internal.h"
 
 using namespace sdl;
+
+namespace sdl {
+int learned_code(sdl_proposer* P, const sdl_problem& r, double tau, int32_t* accept_out, const OmpArgs<float>& omp,
+                 hipStream_t st, int64_t* nfallback_host);
+bool proposer_matches(const sdl_proposer* P, const sdl_problem& r);
+int learned_prepare(sdl_proposer* P, int64_t N);
+}  // namespace sdl
 
 namespace {
 
@@ -107,6 +115,8 @@ struct Opt {
   int prec, schedule, use_graph, check_finite, timing, kernel;
   double stop_rel, dep_eps, pivot_fp64;
   sdl_stats* stats;
+  sdl_proposer* proposer;
+  double tau;
 };
 
 Opt resolve(const sdl_options* o) {
@@ -124,6 +134,8 @@ Opt resolve(const sdl_options* o) {
   r.dep_eps = o->dep_eps >= 0 ? o->dep_eps : 1e-10;
   r.pivot_fp64 = o->pivot_fp64 >= 0 ? o->pivot_fp64 : 1e-3;
   r.stats = o->stats;
+  r.proposer = o->proposer;
+  r.tau = o->tau;
   return r;
 }
 
@@ -268,6 +280,8 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
   a.counters = pl.counters;
   a.sums_side = 0;
   a.sums_part = nullptr;
+  a.index = nullptr;
+  a.count = nullptr;
   return a;
 }
 
@@ -444,13 +458,46 @@ int tmod_update_impl(sdl_problem* p, int nprob, uint32_t sides, const Opt& o, hi
   return finish_call(st, ctx, pl, o, marks, true);
 }
 
+int validate_learned(const sdl_problem* p, int nprob, const Opt& o) {
+  if (!o.proposer) return SDL_OK;
+  if (o.prec != SDL_FP32) return fail(SDL_E_UNSUPPORTED, "the learned proposal runs on FP32 problems");
+  for (int q = 0; q < nprob; ++q) {
+    if (!proposer_matches(o.proposer, p[q]))
+      return fail(SDL_E_SHAPE, "problem %d: shape differs from the proposer's", q);
+    if (!omp_fast_supported<float>(p[q].m1, p[q].m2, p[q].n1, p[q].n2, p[q].s) || !propose_supported(p[q].n1, p[q].n2, p[q].s))
+      return fail(SDL_E_UNSUPPORTED, "problem %d: no register-resident fallback kernel for this shape", q);
+    if (p[q].N > 0 && !p[q].res2) return fail(SDL_E_INVAL, "problem %d: the learned path needs res2", q);
+    SDL_TRY(learned_prepare(o.proposer, p[q].N));
+  }
+  return SDL_OK;
+}
+
+// sparse coding of one problem: learned proposal + fallback when a proposer is given
+template <typename T>
+int run_code(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, Launcher& L) {
+  if constexpr (sizeof(T) == 4) {
+    if (o.proposer) {
+      SDL_TRY(L.begin(0));
+      SDL_TRY(learned_code(o.proposer, r, o.tau, nullptr, omp_args<float>(r, b, o, pl), L.st, nullptr));
+      return L.end();
+    }
+  }
+  return run_omp<T>(r, b, o, pl, 0, L);
+}
+
 template <typename T>
 int one_iteration(sdl_problem* p, int nprob, int K, const Opt& o, const Plan& pl, Launcher& L) {
   for (int q = 0; q < nprob; ++q) {
     const sdl_problem& r = p[q];
     if (r.N == 0) continue;
     const PBuf& b = pl.pb[q];
-    if (o.schedule == 0 && use_fast<T>(r, o)) {
+    if (o.proposer) {
+      SDL_TRY(run_code<T>(r, b, o, pl, L));
+      SDL_TRY(run_rmse<T>(r, b, pl, q, K, L));
+      SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+      SDL_TRY(run_code<T>(r, b, o, pl, L));
+      SDL_TRY(run_update<T>(2, r, b, pl, false, L));
+    } else if (o.schedule == 0 && use_fast<T>(r, o)) {
       // Algorithm 1 with the sums (and the RMSE) computed in the sparse-coding epilogue
       const int rows = omp_fast_partial_rows(r.N, r.m1, r.m2, r.n1, r.n2, r.s);
       SDL_TRY(run_omp<T>(r, b, o, pl, 1, L));
@@ -525,7 +572,7 @@ int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hi
   }
   for (int q = 0; q < nprob; ++q) {
     if (p[q].N == 0) continue;
-    SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, 0, L));
+    SDL_TRY(run_code<T>(p[q], pl.pb[q], o, pl, L));
     SDL_TRY(run_rmse<T>(p[q], pl.pb[q], pl, q, K, L));
   }
   int rc = finish_call(st, ctx, pl, o, marks, true);
@@ -538,6 +585,10 @@ int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hi
 }
 
 }  // namespace
+
+namespace sdl {
+int abi_fail(int st, const char* msg) { return fail(st, "%s", msg); }
+}  // namespace sdl
 
 extern "C" {
 
@@ -554,6 +605,8 @@ void sdl_default_options(sdl_options* o) {
   o->dep_eps = -1.0;
   o->pivot_fp64 = -1.0;
   o->stats = nullptr;
+  o->proposer = nullptr;
+  o->tau = 0.0;
 }
 
 int sdl_sparse_code(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream) {
@@ -578,6 +631,7 @@ int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, cons
   g_err.clear();
   Opt opt = resolve(o);
   SDL_TRY(validate(p, nprob, opt, false));
+  SDL_TRY(validate_learned(p, nprob, opt));
   if (K < 0) return fail(SDL_E_INVAL, "K = %d < 0", K);
   hipStream_t st = (hipStream_t)stream;
   return opt.prec == SDL_FP64 ? learn_impl<double>(p, nprob, K, rmse_trace, opt, st)
@@ -647,6 +701,84 @@ int sdl_set_kernel_variant(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32
   }
   return fail(SDL_E_UNSUPPORTED, "no kernel variant (%d, %d, %d) for this shape", lanes_row, lanes_col,
               waves_per_simd);
+}
+
+int sdl_learned_sparse_code(sdl_proposer* P, const sdl_problem* p, int32_t nprob, int32_t* accept,
+                            const sdl_options* o, void* stream) {
+  g_err.clear();
+  if (!P) return fail(SDL_E_INVAL, "proposer is NULL");
+  Opt opt = resolve(o);
+  opt.prec = SDL_FP32;
+  opt.proposer = P;
+  SDL_TRY(validate(p, nprob, opt, false));
+  SDL_TRY(validate_learned(p, nprob, opt));
+  if (accept && nprob != 1) return fail(SDL_E_INVAL, "accept needs nprob == 1");
+  hipStream_t st = (hipStream_t)stream;
+  Ctx* ctx;
+  SDL_TRY(get_ctx(st, &ctx));
+  Plan pl;
+  layout(p, nprob, sizeof(float), 0, nullptr, &pl);
+  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
+  layout(p, nprob, sizeof(float), 0, ctx->ws, &pl);
+  std::vector<std::pair<int, int>> marks;
+  Launcher L{st, false, ctx, &marks};
+  SDL_TRY(begin_call(st, ctx, pl, nprob));
+  int64_t fb_total = 0, n_total = 0;
+  for (int q = 0; q < nprob; ++q) {
+    if (p[q].N == 0) continue;
+    SDL_TRY(run_prep<float>(p[q], pl.pb[q], L));
+    int64_t fb = 0;
+    SDL_TRY(learned_code(P, p[q], opt.tau, accept, omp_args<float>(p[q], pl.pb[q], opt, pl), st,
+                         opt.stats ? &fb : nullptr));
+    fb_total += fb;
+    n_total += p[q].N;
+  }
+  if (opt.stats) {
+    opt.stats->fallbacks += fb_total;
+    opt.stats->proposals_accepted += n_total - fb_total;
+  }
+  return finish_call(st, ctx, pl, opt, marks, opt.stats != nullptr);
+}
+
+int sdl_proposer_calibrate(sdl_proposer* P, const sdl_problem* prob, double violation, double* tau_out,
+                           void* stream) {
+  g_err.clear();
+  if (!P || !prob || !tau_out) return fail(SDL_E_INVAL, "NULL argument");
+  if (!(violation >= 0.0 && violation < 1.0)) return fail(SDL_E_INVAL, "violation must be in [0, 1)");
+  const sdl_problem& r = *prob;
+  if (!r.res2) return fail(SDL_E_INVAL, "calibration needs res2");
+  const int64_t N = r.N;
+  hipStream_t st = (hipStream_t)stream;
+  sdl_options o;
+  sdl_default_options(&o);
+  o.prec = SDL_FP32;
+  o.tau = 1e300;  // accept every proposal: its residual is what we want
+  SDL_TRY(sdl_learned_sparse_code(P, prob, 1, nullptr, &o, stream));
+  std::vector<float> rp(N), ro(N), y((size_t)N * r.m1 * r.m2);
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(rp.data(), r.res2, sizeof(float) * N, hipMemcpyDeviceToHost));
+  o.tau = 0.0;
+  SDL_TRY(sdl_sparse_code(prob, 1, &o, stream));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(ro.data(), r.res2, sizeof(float) * N, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(y.data(), r.Y, sizeof(float) * y.size(), hipMemcpyDeviceToHost));
+  std::vector<std::pair<double, int>> q(N);
+  for (int64_t k = 0; k < N; ++k) {
+    double yy = 0.0;
+    for (int e = 0; e < r.m1 * r.m2; ++e) yy += (double)y[k * r.m1 * r.m2 + e] * y[k * r.m1 * r.m2 + e];
+    const double ratio = yy > 0 ? rp[k] / yy : 0.0;
+    const int bad = (double)rp[k] > 1.01 * (double)ro[k] ? 1 : 0;
+    q[k] = {ratio, bad};
+  }
+  std::sort(q.begin(), q.end());
+  double tau = 0.0;
+  int64_t nbad = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    nbad += q[i].second;
+    if ((double)nbad <= violation * (double)(i + 1)) tau = q[i].first;
+  }
+  *tau_out = tau;
+  return SDL_OK;
 }
 
 const char* sdl_last_error(void) { return g_err.c_str(); }

@@ -37,6 +37,10 @@ struct OmpArgs {
   // row of (nent + 1) doubles per wave into sums_part (see omp_fast_partial_rows).
   int sums_side;
   double* sums_part;
+  // Register-resident kernel only: code only the signals index[0 .. *count-1] (device
+  // pointers; outputs go to those positions).  Null: all N signals in order.
+  const int32_t* index;
+  const int32_t* count;
 };
 
 // Buffers describing one TMOD half-step for one problem.
