@@ -41,6 +41,57 @@ def omp_bytes_per_signal(m1, m2, s, elem):
     return m1 * m2 * elem + s * (4 + elem) + elem
 
 
+def learned_vs_plain(args, api, oracle, synth):
+    """Learned proposal + 2D-OMP fallback vs plain 2D-OMP, Algorithm 1 on 1M held-out signals
+    of the learned workload (8x8, 16x16 atoms, s = 8), starting at the generating dictionaries;
+    the network is trained on the 2D-OMP supports of 500k signals."""
+    import torch
+
+    w = synth.WORKLOADS["learned_8x8_n16_s8"]
+    d1, d2 = synth.true_dictionaries(w)
+    ntr, nev = 500_000, 1_000_000
+    D1 = torch.from_numpy(d1.T.copy()).cuda()
+    D2 = torch.from_numpy(d2.T.copy()).cuda()
+    Ytr = torch.from_numpy(synth.signals(w, 0, ntr, dtype=np.float32, layout="colmajor")).cuda()
+    tr = api.Problem(Ytr, D1.clone(), D2.clone(), w.s)
+    api.sparse_code(tr)
+    torch.cuda.synchronize()
+    net = api.Proposer(w.m1, w.m2, w.n1, w.n2, hidden=512, seed=7)
+    t0 = time.perf_counter()
+    losses = net.train(Ytr, tr.supp, w.s, epochs=8, batch=256, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    Yev = torch.from_numpy(synth.signals(w, ntr, ntr + nev, dtype=np.float32, layout="colmajor")).cuda()
+    del Ytr, tr
+    cal = api.Problem(Yev[:20000].contiguous(), D1.clone(), D2.clone(), w.s)
+    tau = net.calibrate(cal)
+    st = api.new_stats()
+    api.learned_sparse_code(net, api.Problem(Yev, D1.clone(), D2.clone(), w.s), tau=tau, stats=st)
+    fallback_rate = st.fallbacks / nev
+    K = args.learned_steps
+    out = {"workload": w.name, "N": nev, "steps": K, "train_signals": ntr, "train_epochs": 8,
+           "train_seconds": train_s, "final_train_loss": float(losses[-1]), "tau": tau,
+           "fallback_rate": fallback_rate}
+    nsub = 5000
+    Ysub = synth.signals(w, ntr, ntr + nsub)
+    for name, kw in (("plain", {}), ("learned", {"proposer": net, "tau": tau})):
+        pr = api.Problem(Yev, D1.clone(), D2.clone(), w.s)
+        api.learn(pr, 1, **kw)  # warm-up
+        pr = api.Problem(Yev, D1.clone(), D2.clone(), w.s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.learn(pr, K, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+        r_g = pr.res2[:nsub].double().cpu().numpy()
+        out[name + "_value"] = nev * K / dt
+        out[name + "_rmse_vs_oracle"] = float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean()))
+    out["unit"] = "signals/s per iteration"
+    out["learned_over_plain"] = out["learned_value"] / out["plain_value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,7 +99,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp32_8x8_n16_s8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--cpu-sample", type=int, default=100000)
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -113,12 +167,17 @@ def main():
         ns = min(args.cpu_sample, w.N)
         Yc = synth.signals(w, 0, ns)
         tc0 = time.perf_counter()
-        oracle.learn(Yc, d1, d2, w.s, 1, p=p)
+        oracle.learn(Yc, d1, d2, w.s, args.cpu_iters, p=p)
         tc1 = time.perf_counter()
-        # one iteration (+ the final sparse coding the call includes) over ns signals
-        cpu = {"value": ns / (tc1 - tc0), "unit": "signals/s per iteration", "cores": p, "kind": "oracle",
-               "sample": "first %d signals of the workload, 1 Algorithm-1 iteration plus the final 2D-OMP, "
-                         "FP64, %d threads" % (ns, p)}
+        # K iterations (+ the final sparse coding the call includes) over ns signals
+        cpu = {"value": ns * args.cpu_iters / (tc1 - tc0), "unit": "signals/s per iteration", "cores": p,
+               "kind": "oracle", "seconds": tc1 - tc0,
+               "sample": "first %d signals of the workload, %d Algorithm-1 iterations plus the final 2D-OMP, "
+                         "FP64 oracle, %d threads" % (ns, args.cpu_iters, p)}
+
+    learned = None
+    if not args.no_learned and dtype == torch.float32:
+        learned = learned_vs_plain(args, api, oracle, synth)
 
     out = {
         "metric": "2D-OMP+TMOD signals/s per iteration, learned vs plain at matched RMSE",
@@ -144,6 +203,7 @@ def main():
         "kernel_avg_ms": per_class,
         "rmse_final": float(trace[-1]),
         "rmse_vs_oracle": rmse_ratio,
+        "learned_vs_plain": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
