@@ -194,8 +194,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "path": "plain", "m1": w.m1, "m2": w.m2, "n1": w.n1, "n2": w.n2,
                    "s": w.s, "N": w.N, "snr_db": w.snr_db,
-                   "omp_kernel": ("register-resident lanes %dx%d, %d waves/SIMD" % tuned[:3]) if tuned
-                   else "generic"},
+                   "omp_kernel": ("register-resident lanes %dx%d, %d waves/SIMD%s" %
+                                  (tuned[0], tuned[1], tuned[2], ", refresh on MFMA" if tuned[3] else ""))
+                   if tuned else "generic"},
         "roofline": {"bound": "alu", "kernel": "omp_sparse_code", "achieved": achieved_tflops,
                      "peak": FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6, "unit": "TFLOP/s",
                      "frac": achieved_tflops / (FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6),

@@ -146,20 +146,21 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
 
 /* Kernel configuration currently used for an FP32 shape: lanes per signal split
  * over atom rows (lanes_row) and columns (lanes_col), register budget in waves
- * per SIMD, and the tuned time in ms (0 if not tuned).  Returns 0 if the shape has
- * a register-resident kernel, SDL_E_UNSUPPORTED if it runs on the generic kernel. */
+ * per SIMD, whether the correlation refresh runs on the matrix cores, and the tuned
+ * time in ms (0 if not tuned).  Returns 0 if the shape has a register-resident
+ * kernel, SDL_E_UNSUPPORTED if it runs on the generic kernel. */
 int sdl_tuned_config(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* lanes_row,
-                     int32_t* lanes_col, int32_t* waves_per_simd, double* ms);
+                     int32_t* lanes_col, int32_t* waves_per_simd, int32_t* matrix_core, double* ms);
 
 /* Register-resident kernel variants compiled for an FP32 shape: writes up to `cap`
- * triples (lanes_row, lanes_col, waves_per_simd) to out (host, 3*cap int32) and
- * returns how many exist (0: the shape runs on the generic kernel). */
+ * quadruples (lanes_row, lanes_col, waves_per_simd, matrix_core) to out (host,
+ * 4*cap int32) and returns how many exist (0: the shape runs on the generic kernel). */
 int sdl_kernel_variants(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* out, int32_t cap);
 
 /* Force the variant used for an FP32 shape for the rest of the process (instead of
  * the autotuned or default one).  SDL_E_UNSUPPORTED if no such variant exists. */
 int sdl_set_kernel_variant(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t lanes_row,
-                           int32_t lanes_col, int32_t waves_per_simd);
+                           int32_t lanes_col, int32_t waves_per_simd, int32_t matrix_core);
 
 /* ---- Learned support proposal (not part of the paper; an accelerator in front of 2D-OMP).
  * An MLP maps vec(Y_k)/||Y_k||_F (m1*m2 inputs) through two GELU layers of `hidden` units to

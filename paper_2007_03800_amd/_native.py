@@ -72,11 +72,11 @@ def lib():
         L.sdl_autotune.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p]
         L.sdl_autotune.restype = ctypes.c_int
         ip = ctypes.POINTER(ctypes.c_int32)
-        L.sdl_tuned_config.argtypes = [ctypes.c_int32] * 5 + [ip, ip, ip, ctypes.POINTER(ctypes.c_double)]
+        L.sdl_tuned_config.argtypes = [ctypes.c_int32] * 5 + [ip, ip, ip, ip, ctypes.POINTER(ctypes.c_double)]
         L.sdl_tuned_config.restype = ctypes.c_int
         L.sdl_kernel_variants.argtypes = [ctypes.c_int32] * 5 + [ip, ctypes.c_int32]
         L.sdl_kernel_variants.restype = ctypes.c_int
-        L.sdl_set_kernel_variant.argtypes = [ctypes.c_int32] * 8
+        L.sdl_set_kernel_variant.argtypes = [ctypes.c_int32] * 9
         L.sdl_set_kernel_variant.restype = ctypes.c_int
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.sdl_proposer_create.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.c_uint64, ctypes.POINTER(vp)]

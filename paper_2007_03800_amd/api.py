@@ -150,21 +150,21 @@ def autotune(problems: Problem | Sequence[Problem], reps: int = 5, stream=None, 
 
 
 def tuned_config(m1, m2, n1, n2, s):
-    """(lanes_row, lanes_col, waves_per_simd, tuned_ms) for an FP32 shape, or None (generic kernel)."""
-    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    """(lanes_row, lanes_col, waves_per_simd, matrix_core, tuned_ms) for an FP32 shape, or None."""
+    a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     ms = ctypes.c_double()
     st = _native.lib().sdl_tuned_config(m1, m2, n1, n2, s, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
-                                        ctypes.byref(ms))
+                                        ctypes.byref(d), ctypes.byref(ms))
     if st != 0:
         return None
-    return a.value, b.value, c.value, ms.value
+    return a.value, b.value, c.value, d.value, ms.value
 
 
 def kernel_variants(m1, m2, n1, n2, s):
-    """[(lanes_row, lanes_col, waves_per_simd), ...] compiled for an FP32 shape."""
-    buf = (ctypes.c_int32 * 192)()
+    """[(lanes_row, lanes_col, waves_per_simd, matrix_core), ...] compiled for an FP32 shape."""
+    buf = (ctypes.c_int32 * 256)()
     n = _native.lib().sdl_kernel_variants(m1, m2, n1, n2, s, buf, 64)
-    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(min(n, 64))]
+    return [tuple(buf[4 * i:4 * i + 4]) for i in range(min(n, 64))]
 
 
 def set_kernel_variant(m1, m2, n1, n2, s, variant):

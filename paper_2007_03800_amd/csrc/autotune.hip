@@ -6,7 +6,7 @@
 // HIP events and keeps the fastest for the rest of the process; if the
 // environment variable SDL_TUNE_CACHE names a file, choices are read from it on
 // first use and appended to it after tuning (one line per shape:
-// "m1 m2 n1 n2 s lanes_row lanes_col waves_per_simd ms").
+// "m1 m2 n1 n2 s lanes_row lanes_col waves_per_simd matrix_core ms").
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -32,13 +32,13 @@ std::mutex g_tune_mu;
 std::map<Key, Choice> g_choice;
 bool g_cache_loaded = false;
 
-int find_variant(int m1, int m2, int n1, int n2, int s, int lr, int lc, int wpe) {
+int find_variant(int m1, int m2, int n1, int n2, int s, int lr, int lc, int wpe, int mfma) {
   int ids[32];
   const int n = omp_fast_variants(m1, m2, n1, n2, s, ids, 32);
   for (int i = 0; i < n && i < 32; ++i) {
-    int a, b, c;
-    omp_fast_variant_info(ids[i], &a, &b, &c);
-    if (a == lr && b == lc && c == wpe) return ids[i];
+    int a, b, c, d;
+    omp_fast_variant_info(ids[i], &a, &b, &c, &d);
+    if (a == lr && b == lc && c == wpe && d == mfma) return ids[i];
   }
   return -1;
 }
@@ -50,10 +50,10 @@ void load_cache_locked() {
   if (!path || !*path) return;
   FILE* f = fopen(path, "r");
   if (!f) return;
-  int m1, m2, n1, n2, s, lr, lc, wpe;
+  int m1, m2, n1, n2, s, lr, lc, wpe, mf;
   double ms;
-  while (fscanf(f, "%d %d %d %d %d %d %d %d %lf", &m1, &m2, &n1, &n2, &s, &lr, &lc, &wpe, &ms) == 9) {
-    const int id = find_variant(m1, m2, n1, n2, s, lr, lc, wpe);
+  while (fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &m1, &m2, &n1, &n2, &s, &lr, &lc, &wpe, &mf, &ms) == 10) {
+    const int id = find_variant(m1, m2, n1, n2, s, lr, lc, wpe, mf);
     if (id >= 0) g_choice[Key(m1, m2, n1, n2, s)] = Choice{id, ms};
   }
   fclose(f);
@@ -64,10 +64,10 @@ void append_cache(const Key& k, int id, double ms) {
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  int lr, lc, wpe;
-  omp_fast_variant_info(id, &lr, &lc, &wpe);
-  fprintf(f, "%d %d %d %d %d %d %d %d %.6f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-          std::get<4>(k), lr, lc, wpe, ms);
+  int lr, lc, wpe, mf;
+  omp_fast_variant_info(id, &lr, &lc, &wpe, &mf);
+  fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+          std::get<4>(k), lr, lc, wpe, mf, ms);
   fclose(f);
 }
 
@@ -138,7 +138,7 @@ hipError_t autotune_problem(const OmpArgs<float>& a, hipStream_t st, int reps, i
   return hipSuccess;
 }
 
-bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* wpe, double* ms) {
+bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* wpe, int* mfma, double* ms) {
   int id;
   double t = 0.0;
   {
@@ -154,7 +154,7 @@ bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* 
     }
   }
   if (id < 0) return false;
-  omp_fast_variant_info(id, lr, lc, wpe);
+  omp_fast_variant_info(id, lr, lc, wpe, mfma);
   if (ms) *ms = t;
   return true;
 }

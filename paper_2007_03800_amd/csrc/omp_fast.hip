@@ -26,6 +26,9 @@
 //    G_aa - |w|^2).
 #include <limits.h>
 
+#include <iterator>
+#include <vector>
+
 #include "sdl_internal.h"
 
 namespace sdl {
@@ -493,16 +496,28 @@ hipError_t launch_cfg(const OmpArgs<float>& a, hipStream_t st) {
   X(16, 16, 32, 32, 16, 4, 4, 1) X(16, 16, 32, 32, 16, 4, 8, 2)
 
 struct Variant {
-  int m1, m2, n1, n2, s, lr, lc, wpe;
+  int m1, m2, n1, n2, s, lr, lc, wpe, mfma;
   hipError_t (*launch)(const OmpArgs<float>&, hipStream_t);
 };
 
-const Variant kVariants[] = {
-#define X(A_, B_, C_, D_, E_, F_, G_, H_) {A_, B_, C_, D_, E_, F_, G_, H_, &launch_cfg<Cfg<A_, B_, C_, D_, E_, F_, G_, H_>>},
+const Variant kValuVariants[] = {
+#define X(A_, B_, C_, D_, E_, F_, G_, H_) {A_, B_, C_, D_, E_, F_, G_, H_, 0, &launch_cfg<Cfg<A_, B_, C_, D_, E_, F_, G_, H_>>},
     SDL_FAST_VARIANTS(X)
 #undef X
 };
-constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// all variants: the VALU layouts above, then the matrix-core layouts (lanes 1 x 4)
+const std::vector<Variant>& variants() {
+  static const std::vector<Variant> v = [] {
+    std::vector<Variant> out(std::begin(kValuVariants), std::end(kValuVariants));
+    for (int i = 0; i < mfma_variants_count; ++i) {
+      const MfmaVariant& m = mfma_variants_table[i];
+      out.push_back(Variant{m.m1, m.m2, m.n1, m.n2, m.s, 1, 4, m.wpe, 1, m.launch});
+    }
+    return out;
+  }();
+  return v;
+}
 
 }  // namespace
 
@@ -519,7 +534,9 @@ bool omp_fast_supported<double>(int, int, int, int, int) {
 int omp_fast_partial_rows(int64_t N, int m1, int m2, int n1, int n2, int s) {
   const int id = omp_fast_choice(m1, m2, n1, n2, s);
   if (id < 0) return 0;
-  return (int)fast_blocks(N, 64 / (kVariants[id].lr * kVariants[id].lc), kVariants[id].wpe);
+  const Variant& x = variants()[id];
+  if (x.mfma) return (int)mfma_partial_rows(N, x.wpe);
+  return (int)fast_blocks(N, 64 / (x.lr * x.lc), x.wpe);
 }
 
 int omp_fast_max_partial_rows() { return kFastMaxBlocks; }
@@ -528,14 +545,18 @@ hipError_t omp_fast_init_device() {
   int dev = 0, n = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess && n > 0) g_num_cus = n;
+  if (e == hipSuccess && n > 0) {
+    g_num_cus = n;
+    mfma_set_cus(n);
+  }
   return e;
 }
 
 int omp_fast_variants(int m1, int m2, int n1, int n2, int s, int* ids, int cap) {
   int n = 0;
-  for (int v = 0; v < kNumVariants; ++v) {
-    const Variant& x = kVariants[v];
+  const std::vector<Variant>& vs = variants();
+  for (int v = 0; v < (int)vs.size(); ++v) {
+    const Variant& x = vs[v];
     if (x.m1 == m1 && x.m2 == m2 && x.n1 == n1 && x.n2 == n2 && x.s == s) {
       if (ids && n < cap) ids[n] = v;
       ++n;
@@ -544,16 +565,18 @@ int omp_fast_variants(int m1, int m2, int n1, int n2, int s, int* ids, int cap) 
   return n;
 }
 
-void omp_fast_variant_info(int id, int* lr, int* lc, int* wpe) {
-  *lr = kVariants[id].lr;
-  *lc = kVariants[id].lc;
-  *wpe = kVariants[id].wpe;
+void omp_fast_variant_info(int id, int* lr, int* lc, int* wpe, int* mfma) {
+  const Variant& x = variants()[id];
+  *lr = x.lr;
+  *lc = x.lc;
+  *wpe = x.wpe;
+  if (mfma) *mfma = x.mfma;
 }
 
 hipError_t launch_omp_fast_variant(int id, const OmpArgs<float>& a, hipStream_t st) {
-  if (id < 0 || id >= kNumVariants) return hipErrorInvalidValue;
+  if (id < 0 || id >= (int)variants().size()) return hipErrorInvalidValue;
   if (a.N == 0) return hipSuccess;
-  return kVariants[id].launch(a, st);
+  return variants()[id].launch(a, st);
 }
 
 template <>

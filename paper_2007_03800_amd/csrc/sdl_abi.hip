@@ -667,14 +667,15 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
 }
 
 int sdl_tuned_config(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* lanes_row,
-                     int32_t* lanes_col, int32_t* waves_per_simd, double* ms) {
-  int lr = 0, lc = 0, wpe = 0;
+                     int32_t* lanes_col, int32_t* waves_per_simd, int32_t* matrix_core, double* ms) {
+  int lr = 0, lc = 0, wpe = 0, mf = 0;
   double t = 0.0;
-  if (!tuned_config(m1, m2, n1, n2, s, &lr, &lc, &wpe, &t))
+  if (!tuned_config(m1, m2, n1, n2, s, &lr, &lc, &wpe, &mf, &t))
     return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for this shape");
   if (lanes_row) *lanes_row = lr;
   if (lanes_col) *lanes_col = lc;
   if (waves_per_simd) *waves_per_simd = wpe;
+  if (matrix_core) *matrix_core = mf;
   if (ms) *ms = t;
   return SDL_OK;
 }
@@ -683,18 +684,18 @@ int sdl_kernel_variants(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t 
   int ids[64];
   const int n = omp_fast_variants(m1, m2, n1, n2, s, ids, 64);
   for (int i = 0; i < n && i < cap && i < 64 && out; ++i)
-    omp_fast_variant_info(ids[i], &out[3 * i], &out[3 * i + 1], &out[3 * i + 2]);
+    omp_fast_variant_info(ids[i], &out[4 * i], &out[4 * i + 1], &out[4 * i + 2], &out[4 * i + 3]);
   return n;
 }
 
 int sdl_set_kernel_variant(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t lanes_row,
-                           int32_t lanes_col, int32_t waves_per_simd) {
+                           int32_t lanes_col, int32_t waves_per_simd, int32_t matrix_core) {
   int ids[64];
   const int n = omp_fast_variants(m1, m2, n1, n2, s, ids, 64);
   for (int i = 0; i < n && i < 64; ++i) {
-    int lr, lc, wpe;
-    omp_fast_variant_info(ids[i], &lr, &lc, &wpe);
-    if (lr == lanes_row && lc == lanes_col && wpe == waves_per_simd) {
+    int lr, lc, wpe, mf;
+    omp_fast_variant_info(ids[i], &lr, &lc, &wpe, &mf);
+    if (lr == lanes_row && lc == lanes_col && wpe == waves_per_simd && mf == matrix_core) {
       omp_fast_set_choice(m1, m2, n1, n2, s, ids[i]);
       return SDL_OK;
     }

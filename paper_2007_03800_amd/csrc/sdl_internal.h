@@ -62,9 +62,21 @@ template <typename T>
 bool omp_fast_supported(int m1, int m2, int n1, int n2, int s);
 template <typename T>
 hipError_t launch_omp_fast(const OmpArgs<T>& a, hipStream_t st);
-// Register-resident variants for a shape: writes up to cap variant ids, returns the count.
+// Matrix-core variants (omp_mfma.hip): four lanes per signal, refresh on 4x4x1 MFMA.
+struct MfmaVariant {
+  int m1, m2, n1, n2, s, wpe;
+  hipError_t (*launch)(const OmpArgs<float>&, hipStream_t);
+};
+extern MfmaVariant mfma_variants_table[];
+extern const int mfma_variants_count;
+int64_t mfma_partial_rows(int64_t N, int wpe);
+void mfma_set_cus(int n);
+
+// Register-resident variants for a shape (VALU layouts and matrix-core layouts): writes
+// up to cap variant ids, returns the count.  Info: lane split over atom rows/columns,
+// register budget in waves per SIMD, and whether the refresh runs on the matrix cores.
 int omp_fast_variants(int m1, int m2, int n1, int n2, int s, int* ids, int cap);
-void omp_fast_variant_info(int id, int* lr, int* lc, int* wpe);
+void omp_fast_variant_info(int id, int* lr, int* lc, int* wpe, int* mfma);
 hipError_t launch_omp_fast_variant(int id, const OmpArgs<float>& a, hipStream_t st);
 // Variant used for a shape: the autotuned one if tuned in this process, else the first listed.
 int omp_fast_choice(int m1, int m2, int n1, int n2, int s);
@@ -75,7 +87,7 @@ int omp_fast_max_partial_rows();
 hipError_t omp_fast_init_device();
 void omp_fast_set_choice(int m1, int m2, int n1, int n2, int s, int id);
 hipError_t autotune_problem(const OmpArgs<float>& a, hipStream_t st, int reps, int* chosen, double* best_ms);
-bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* wpe, double* ms);
+bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* wpe, int* mfma, double* ms);
 size_t omp_generic_lds_bytes(int m1, int m2, int n1, int n2, int s, size_t elem);
 hipError_t omp_generic_init_device();
 

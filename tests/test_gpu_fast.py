@@ -50,5 +50,5 @@ def test_autotune_picks_a_variant(rng):
     pr = api.Problem.from_math(Y, d1, d2, s, dtype=torch.float32)
     api.autotune(pr, reps=3)
     cfg = api.tuned_config(m1, m2, n1, n2, s)
-    assert cfg is not None and cfg[:3] in api.kernel_variants(m1, m2, n1, n2, s) and cfg[3] > 0
+    assert cfg is not None and cfg[:4] in api.kernel_variants(m1, m2, n1, n2, s) and cfg[4] > 0
     assert api.tuned_config(5, 5, 7, 7, 3) is None
