@@ -8,8 +8,8 @@ default workload is the image-patch-shaped FP32 problem: 8x8 signals, D1 and D2
 Prints ONE JSON line.  Also reports, for the dominant kernel (the 2D-OMP
 sparse-coding kernel), its average device time measured with HIP events on the
 stream it runs on, the algorithmic FLOP count per launch and the fraction of the
-FP32 vector peak; and the FP64 CPU oracle timed on a bounded sample on this
-host's cores.
+FP32 peak (157.3 TFLOP/s for both the vector units and the matrix cores); and the
+FP64 CPU oracle timed on a bounded sample on this host's cores.
 """
 from __future__ import annotations
 
@@ -36,9 +36,50 @@ def omp_flops_per_signal(m1, m2, n1, n2, s):
     return f_c + f_greedy
 
 
+def sums_flops_per_signal(m1, m2, n1, n2, s):
+    """Algorithmic FLOPs of one signal's contribution to the TMOD sums that the
+    sparse-coding launch accumulates in its epilogue (Corollary 1, dense products,
+    symmetric A counted in full), averaged over the D1-side and D2-side launches:
+    T = X D2^T from s nonzeros, A += T T^T, B += Y T^T (and the mirror for D2)."""
+    side1 = 2 * s * m2 + 2 * n1 * n1 * m2 + 2 * m1 * n1 * m2
+    side2 = 2 * s * m1 + 2 * n2 * n2 * m1 + 2 * m2 * n2 * m1
+    return (side1 + side2) / 2
+
+
 def omp_bytes_per_signal(m1, m2, s, elem):
     # Y read once, supp (int32) + coef + res2 written
     return m1 * m2 * elem + s * (4 + elem) + elem
+
+
+def kernel_symbol(w, tuned):
+    """Name of the sparse-coding kernel instantiation the autotuner chose, as the
+    profiler lists it."""
+    if not tuned:
+        return "omp_generic_kernel"
+    lr, lc, wpe, mfma = tuned[:4]
+    if mfma:
+        return "omp_mfma_kernel<MCfg<%d, %d, %d, %d, %d, %d>>" % (w.m1, w.m2, w.n1, w.n2, w.s, wpe)
+    return "omp_fast_kernel<Cfg<%d, %d, %d, %d, %d, %d, %d, %d>>" % (w.m1, w.m2, w.n1, w.n2, w.s, lr, lc, wpe)
+
+
+def measured_traffic(w, symbol):
+    """HBM bytes per launch of the sparse-coding kernel from the committed hardware-counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a copy of
+    known size), or None when there is none for this kernel and workload or the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "omp_mfma_%s_traffic.json" % w.name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel") != symbol:
+        return None
+    h = hashlib.sha256()
+    for src in t["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return t["bytes_per_launch"] if h.hexdigest() == t["source_sha256"] else None
 
 
 def learned_vs_plain(args, api, oracle, synth):
@@ -103,6 +144,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-steps", type=int, default=5)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one elementwise FP32 copy of MIB MiB (reads and writes MIB MiB): "
+                         "the reference dispatch that scales hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -113,6 +157,14 @@ def main():
 
     import oracle
     from paper_2007_03800_amd import api, synth
+
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     w = synth.WORKLOADS[args.workload]
     dtype = torch.float32 if not args.workload.startswith("fp64") else torch.float64
@@ -149,7 +201,9 @@ def main():
     api.learn(pr2, min(args.steps, 5), timing=1, stats=st)
     sd = st.as_dict()
     omp_ms = sd["kernel_ms"]["sparse_code"] / sd["kernel_launches"]["sparse_code"]
-    flops = omp_flops_per_signal(w.m1, w.m2, w.n1, w.n2, w.s) * w.N
+    # the launch codes every signal and accumulates its share of the next update's sums
+    flops = (omp_flops_per_signal(w.m1, w.m2, w.n1, w.n2, w.s) +
+             sums_flops_per_signal(w.m1, w.m2, w.n1, w.n2, w.s)) * w.N
     achieved_tflops = flops / (omp_ms * 1e-3) / 1e12
     per_class = {k: round(v / sd["kernel_launches"][k], 4) for k, v in sd["kernel_ms"].items()}
 
@@ -179,6 +233,7 @@ def main():
     if not args.no_learned and dtype == torch.float32:
         learned = learned_vs_plain(args, api, oracle, synth)
 
+    symbol = kernel_symbol(w, tuned)
     out = {
         "metric": "2D-OMP+TMOD signals/s per iteration, learned vs plain at matched RMSE",
         "value": value,
@@ -197,10 +252,12 @@ def main():
                    "omp_kernel": ("register-resident lanes %dx%d, %d waves/SIMD%s" %
                                   (tuned[0], tuned[1], tuned[2], ", refresh on MFMA" if tuned[3] else ""))
                    if tuned else "generic"},
-        "roofline": {"bound": "alu", "kernel": "omp_sparse_code", "achieved": achieved_tflops,
+        "roofline": {"bound": "mfma" if tuned and tuned[3] else "alu",
+                     "kernel": symbol, "achieved": achieved_tflops,
                      "peak": FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6, "unit": "TFLOP/s",
                      "frac": achieved_tflops / (FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6),
-                     "traffic": None, "avg_ms": omp_ms, "flops_per_launch": flops},
+                     "traffic": measured_traffic(w, symbol), "traffic_unit": "bytes/launch",
+                     "avg_ms": omp_ms, "flops_per_launch": flops},
         "kernel_avg_ms": per_class,
         "rmse_final": float(trace[-1]),
         "rmse_vs_oracle": rmse_ratio,

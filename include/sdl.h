@@ -136,8 +136,9 @@ int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, cons
 /* Autotuner (no counterpart in the paper; a property of this GPU implementation):
  * for every FP32 problem whose shape has register-resident kernel variants
  * (different numbers of lanes per signal and register budgets), run each variant
- * `reps` times on the problem's own signals, timed with HIP events on `stream`,
- * and keep the fastest for all later calls in this process.  The problem's
+ * `reps` times on the problem's own signals, timed with HIP events on `stream`
+ * with the D1-update sums epilogue that sdl_learn fuses into the kernel, and keep
+ * the fastest for all later calls in this process.  The problem's
  * supp/coef/res2 are overwritten with valid codes.  If the environment variable
  * SDL_TUNE_CACHE names a file, choices are loaded from it on first use and
  * appended after tuning.  FP64 problems and shapes without variants are skipped.

@@ -658,6 +658,9 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
     if (p[q].N == 0 || !omp_fast_supported<float>(p[q].m1, p[q].m2, p[q].n1, p[q].n2, p[q].s)) continue;
     SDL_TRY(run_prep<float>(p[q], pl.pb[q], L));
     OmpArgs<float> a = omp_args<float>(p[q], pl.pb[q], opt, pl);
+    // timed as the learning loop runs it: with the D1-update sums epilogue
+    a.sums_side = 1;
+    a.sums_part = pl.pb[q].part;
     int id;
     double ms;
     HIP_TRY(autotune_problem(a, st, reps, &id, &ms));
