@@ -67,6 +67,7 @@ int get_ctx(hipStream_t st, Ctx** out) {
     c->device = dev;
     hipError_t e = omp_generic_init_device();
     if (e == hipSuccess) e = tmod_sums_init_device();
+    if (e == hipSuccess) e = tmod_solve_init_device();
     if (e == hipSuccess) e = omp_fast_init_device();
     if (e != hipSuccess) {
       delete c;
@@ -321,18 +322,25 @@ int run_reduce_solve(int side, const sdl_problem& r, const PBuf& b, const Plan& 
                      int rmse_q, int K, Launcher& L) {
   const int na = side == 1 ? r.n1 : r.n2, mr = side == 1 ? r.m1 : r.m2;
   const int nent = na * na + mr * na;
-  SDL_TRY(L.begin(2));
-  HIP_TRY(launch_reduce_partials(b.part, rows, nent + (with_res2 ? 1 : 0), b.stage, b.sums, L.st));
-  SDL_TRY(L.end());
+  const int ld = nent + (with_res2 ? 1 : 0);
+  const double* src = nullptr;
+  int nrow = rows;
+  if (rows > 0) {
+    SDL_TRY(L.begin(2));
+    hipError_t e;
+    nrow = launch_reduce_stage1(b.part, rows, ld, b.stage, &src, L.st, &e);
+    HIP_TRY(e);
+    SDL_TRY(L.end());
+  }
   RmseOut ro{nullptr, nullptr, 0, 0, 0.0};
   if (rmse_q >= 0) ro = RmseOut{pl.trace, pl.iter + rmse_q, rmse_q * (K + 1), nent, (double)r.N * r.m1 * r.m2};
   SDL_TRY(L.begin(3));
   if (side == 1)
-    HIP_TRY(launch_tmod_solve<T>(b.sums, r.m1, r.n1, r.D1, (T*)b.Dc1, b.G1_64, (T*)b.G1c, b.w, pl.status,
-                                 pl.counters, ro, L.st));
+    HIP_TRY(launch_tmod_solve<T>(src, nrow, ld, b.sums, r.m1, r.n1, r.D1, (T*)b.Dc1, b.G1_64, (T*)b.G1c, b.w,
+                                 pl.status, pl.counters, ro, L.st));
   else
-    HIP_TRY(launch_tmod_solve<T>(b.sums, r.m2, r.n2, r.D2, (T*)b.Dc2, b.G2_64, (T*)b.G2c, b.w, pl.status,
-                                 pl.counters, ro, L.st));
+    HIP_TRY(launch_tmod_solve<T>(src, nrow, ld, b.sums, r.m2, r.n2, r.D2, (T*)b.Dc2, b.G2_64, (T*)b.G2c, b.w,
+                                 pl.status, pl.counters, ro, L.st));
   return L.end();
 }
 

@@ -96,9 +96,12 @@ int tmod_num_blocks_for(int64_t N, int na, int mr, int mc);
 hipError_t tmod_sums_init_device();
 template <typename T>
 hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, hipStream_t st);
-// out[e] = sum_b part[b][e] in a fixed order (two stages when P > 64; stage holds
-// reduce_stage_rows(P) x nent doubles).
-hipError_t launch_reduce_partials(const double* part, int P, int nent, double* stage, double* out, hipStream_t st);
+// First stage of the fixed-order reduction of P partial rows (row stride ld): when P is
+// large, consecutive chunks of rows are summed in row order into stage (which holds
+// reduce_stage_rows(P) rows); returns the number of rows the solve kernel still has to
+// sum and points *src at them (part itself when P is small, then nothing is launched).
+int launch_reduce_stage1(const double* part, int P, int ld, double* stage, const double** src, hipStream_t st,
+                         hipError_t* err);
 int reduce_stage_rows(int P);
 // Optional RMSE output of the solve kernel: trace[*counter + offset] = sqrt(sums[idx] / denom), then ++*counter.
 struct RmseOut {
@@ -108,10 +111,15 @@ struct RmseOut {
   int idx;
   double denom;
 };
-// Solve + normalise (one wavefront). D: the dictionary being updated (mr x na FP64, in/out).
+// Last reduction stage + solve + normalise (one workgroup): sums (ld doubles) = the
+// row-order sum of the nrow rows at src; D: the dictionary being updated (mr x na
+// FP64, in/out).  tmod_solve_init_device raises the kernel's LDS limit (call once per
+// device).
 template <typename T>
-hipError_t launch_tmod_solve(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
-                             int* status, unsigned long long* counters, const RmseOut& r, hipStream_t st);
+hipError_t launch_tmod_solve(const double* src, int nrow, int ld, double* sums, int mr, int na, double* D, T* Dc,
+                             double* G64, T* Gc, double* w, int* status, unsigned long long* counters,
+                             const RmseOut& r, hipStream_t st);
+hipError_t tmod_solve_init_device();
 template <typename T>
 hipError_t launch_dict_prep(const double* D, int mr, int na, T* Dc, double* G64, T* Gc, hipStream_t st);
 template <typename T>

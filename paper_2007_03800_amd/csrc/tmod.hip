@@ -37,28 +37,32 @@ __global__ void reduce_stage1_kernel(const double* __restrict__ part, int P, int
   stage[(size_t)c * nent + e] = v;
 }
 
-__global__ void reduce_stage2_kernel(const double* __restrict__ stage, int nchunk, int nent, double* out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nent) return;
-  double v = 0.0;
-  for (int c = 0; c < nchunk; ++c) v += stage[(size_t)c * nent + e];
-  out[e] = v;
-}
+constexpr int kSolveThreads = 512;
+constexpr int kDirectRows = 2 * kChunk;  // up to this many partial rows the solve sums them itself
 
-// Solve + normalise on one wavefront; optionally turn the reduced sum of squared
-// residuals (sums[r.idx]) into the RMSE of the sweep that produced the codes.
+// The master step of Algorithm 1 (steps 2 and 4) in one workgroup: the last stage of
+// the fixed-order reduction, sums[e] = sum over the nrow rows of src (row stride ld)
+// in row order, then the solve and normalisation on the reduced [A | B]; optionally
+// the reduced sum of squared residuals (sums[r.idx]) becomes the RMSE of the sweep
+// that produced the codes.
 template <typename T>
-__global__ void __launch_bounds__(kWave)
-    tmod_solve_kernel(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
-                      int* status, unsigned long long* counters, RmseOut r) {
+__global__ void __launch_bounds__(kSolveThreads)
+    tmod_solve_kernel(const double* __restrict__ src, int nrow, int ld, double* sums, int mr, int na, double* D,
+                      T* Dc, double* G64, T* Gc, double* w, int* status, unsigned long long* counters, RmseOut r) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int lane = threadIdx.x;
-  if (r.trace && lane == 0) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < ld; e += blockDim.x) {
+    double v = 0.0;
+    for (int b = 0; b < nrow; ++b) v += src[(size_t)b * ld + e];
+    sums[e] = v;
+  }
+  __syncthreads();
+  if (r.trace && tid == 0) {
     const int it = *r.counter;
     r.trace[(size_t)it + r.offset] = r.denom > 0 ? sqrt(sums[r.idx] / r.denom) : 0.0;
     *r.counter = it + 1;
   }
-  solve_update<T>(sums, mr, na, D, Dc, G64, Gc, w, status, counters, smem_raw, lane);
+  solve_update_block<T>(sums, mr, na, D, Dc, G64, Gc, w, status, counters, smem_raw, tid, blockDim.x);
 }
 
 template <typename T>
@@ -121,27 +125,38 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
 
 }  // namespace
 
-hipError_t launch_reduce_partials(const double* part, int P, int nent, double* stage, double* out,
-                                 hipStream_t st) {
-  const int nchunk = (P + kChunk - 1) / kChunk;
-  const dim3 g1((nent + 255) / 256, nchunk);
-  if (nchunk == 1) {
-    hipLaunchKernelGGL(reduce_stage1_kernel, g1, dim3(256), 0, st, part, P, nent, out);
-    return hipGetLastError();
+int launch_reduce_stage1(const double* part, int P, int ld, double* stage, const double** src, hipStream_t st,
+                         hipError_t* err) {
+  *err = hipSuccess;
+  if (P <= kDirectRows) {
+    *src = part;
+    return P;
   }
-  hipLaunchKernelGGL(reduce_stage1_kernel, g1, dim3(256), 0, st, part, P, nent, stage);
-  hipLaunchKernelGGL(reduce_stage2_kernel, dim3((nent + 255) / 256), dim3(256), 0, st, stage, nchunk, nent, out);
-  return hipGetLastError();
+  const int nchunk = (P + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(reduce_stage1_kernel, dim3((ld + 255) / 256, nchunk), dim3(256), 0, st, part, P, ld, stage);
+  *err = hipGetLastError();
+  *src = stage;
+  return nchunk;
 }
 
 int reduce_stage_rows(int P) { return (P + kChunk - 1) / kChunk; }
 
 template <typename T>
-hipError_t launch_tmod_solve(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
-                             int* status, unsigned long long* counters, const RmseOut& r, hipStream_t st) {
-  hipLaunchKernelGGL(tmod_solve_kernel<T>, dim3(1), dim3(kWave), solve_lds_bytes(na, mr), st, sums, mr, na, D, Dc,
-                     G64, Gc, w, status, counters, r);
+hipError_t launch_tmod_solve(const double* src, int nrow, int ld, double* sums, int mr, int na, double* D, T* Dc,
+                             double* G64, T* Gc, double* w, int* status, unsigned long long* counters,
+                             const RmseOut& r, hipStream_t st) {
+  hipLaunchKernelGGL(tmod_solve_kernel<T>, dim3(1), dim3(kSolveThreads), solve_lds_bytes(na, mr), st, src, nrow, ld,
+                     sums, mr, na, D, Dc, G64, Gc, w, status, counters, r);
   return hipGetLastError();
+}
+
+hipError_t tmod_solve_init_device() {
+  const int bytes = (int)solve_lds_bytes(SDL_MAX_N, SDL_MAX_M);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&tmod_solve_kernel<float>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&tmod_solve_kernel<double>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <typename T>
@@ -190,8 +205,8 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st) {
 }
 
 #define SDL_INST(T)                                                                                            \
-  template hipError_t launch_tmod_solve<T>(const double*, int, int, double*, T*, double*, T*, double*, int*,  \
-                                           unsigned long long*, const RmseOut&, hipStream_t);                 \
+  template hipError_t launch_tmod_solve<T>(const double*, int, int, double*, int, int, double*, T*, double*, T*, \
+                                           double*, int*, unsigned long long*, const RmseOut&, hipStream_t);  \
   template hipError_t launch_dict_prep<T>(const double*, int, int, T*, double*, T*, hipStream_t);             \
   template hipError_t launch_rescale<T>(int, int, int, int64_t, const int32_t*, T*, const double*,            \
                                         hipStream_t);                                                         \

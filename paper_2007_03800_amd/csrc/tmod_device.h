@@ -9,12 +9,6 @@ namespace sdl {
 
 constexpr double kSpdRelTol = 1e-12;  // Cholesky pivot <= tol * diagonal entry -> not positive definite
 
-__device__ inline void wave_fence_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // D (mr x na FP64) -> compute-type copy, FP64 and compute-type Gram D^T D; threads t0..t0+nt-1.
 template <typename T>
 __device__ void write_copies(const double* D, int mr, int na, T* Dc, double* G64, T* Gc, int t, int nt) {
@@ -28,116 +22,100 @@ __device__ void write_copies(const double* D, int mr, int na, T* Dc, double* G64
   }
 }
 
-// LDS bytes the solve needs for na atoms and mr rows.
+// LDS bytes the block solve needs for na atoms and mr rows: the augmented system
+// (na rows of na + mr entries, padded), the new dictionary, the pivots' reference
+// diagonal and the used-atom list.
 __host__ __device__ inline size_t solve_lds_bytes(int na, int mr) {
-  return sizeof(double) * (2 * (size_t)na * (na + 1) + 2 * (size_t)na * (mr + 1) + na + (size_t)mr * na) +
-         sizeof(int) * na + 16;
+  return sizeof(double) * ((size_t)na * (na + mr + 1) + (size_t)mr * na + na) + sizeof(int) * (na + 1) + 16;
 }
 
-// One wavefront (lane = 0..63).  sums = [A (na x na) | B (mr x na)], column-major,
-// A = the update's Gram sum, B = its right-hand side.  Atoms with A_ii = 0 are used by
-// no code: the system decouples exactly and they keep their old value.  On the used
-// set, D* A_UU = B_U is solved by FP64 Cholesky; each solved column is normalised
-// (w_i = its norm; a zero column keeps the old atom).  A pivot below kSpdRelTol times
-// its diagonal entry marks the sum as not positive definite: D is left unchanged and
-// the singular status bit is set.  smem: solve_lds_bytes(na, mr) bytes.
+// Whole workgroup (tid = 0..nt-1).  sums = [A (na x na) | B (mr x na)], column-major,
+// A = the update's Gram sum, B = its right-hand side (global memory, written by the
+// caller before a block barrier).  Atoms with A_ii = 0 are used by no code: the
+// system decouples exactly and they keep their old value.  On the used set U the
+// symmetric positive definite system A_UU D*^T = B_U^T is solved by Gauss-Jordan
+// elimination without pivoting on the augmented matrix [A_UU | B_U^T]: step k
+// removes column k from every other row using row k as it stands, so each entry is
+// written by one thread per step and one barrier per step suffices.  The pivot of
+// step k is the k-th Schur complement diagonal, the same quantity a Cholesky
+// factorisation takes the root of; a pivot below kSpdRelTol times its diagonal entry
+// marks the sum as not positive definite: D is left unchanged and the singular
+// status bit is set.  Each solved column is then normalised (w_i = its norm; a zero
+// column keeps the old atom), and D, its compute-type copy and the Gram matrix D^T D
+// are rewritten.  smem: solve_lds_bytes(na, mr) bytes.
 template <typename T>
-__device__ void solve_update(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc, double* w,
-                             int* status, unsigned long long* counters, unsigned char* smem, int lane) {
-  const int ldc = na + 1, ldx = mr + 1;
-  double* C = reinterpret_cast<double*>(smem);  // Schur complement being reduced
-  double* Lf = C + (size_t)na * ldc;              // Cholesky factor, written once per column
-  double* X = Lf + (size_t)na * ldc;              // X[k*ldx + p]: right-hand sides, atom k, row p
-  double* Z = X + (size_t)na * ldx;               // finished rows of the triangular solves
-  double* diag0 = Z + (size_t)na * ldx;
-  double* Dn = diag0 + na;  // the new dictionary, mr x na column-major
-  int* U = reinterpret_cast<int*>(Dn + (size_t)mr * na);
+__device__ void solve_update_block(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc,
+                                   double* w, int* status, unsigned long long* counters, unsigned char* smem,
+                                   int tid, int nt) {
+  const int ldm = na + mr + 1;
+  double* M = reinterpret_cast<double*>(smem);  // M[k * ldm + c], c < nu: A_UU, c >= nu: B_U^T
+  double* Dn = M + (size_t)na * ldm;             // new dictionary, mr x na column-major
+  double* diag0 = Dn + (size_t)mr * na;
+  int* U = reinterpret_cast<int*>(diag0 + na);
+  int* nu_s = U + na;
   const double* A = sums;
   const double* B = sums + na * na;
-  const bool used = lane < na && A[lane + na * lane] > 0.0;
-  const unsigned long long mask = __ballot(used);
-  const int nu = __popcll(mask);
-  if (used) U[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
-  if (lane == 0 && nu < na) atomicAdd(&counters[kCtrUnusedAtoms], (unsigned long long)(na - nu));
-  wave_fence_sync();
-  for (int e = lane; e < nu * nu; e += kWave) {
-    const int k = e % nu, l = e / nu;
-    C[k * ldc + l] = A[U[k] + na * U[l]];
-    if (k == l) diag0[k] = C[k * ldc + k];
+  if (tid < kWave) {
+    const bool used = tid < na && A[tid + na * tid] > 0.0;
+    const unsigned long long mask = __ballot(used);
+    const int nu = __popcll(mask);
+    if (used) U[__popcll(mask & ((1ull << tid) - 1ull))] = tid;
+    if (tid == 0) {
+      *nu_s = nu;
+      if (nu < na) atomicAdd(&counters[kCtrUnusedAtoms], (unsigned long long)(na - nu));
+    }
   }
-  for (int e = lane; e < nu * mr; e += kWave) {
-    const int k = e % nu, p = e / nu;
-    X[k * ldx + p] = B[p + mr * U[k]];
+  for (int e = tid; e < mr * na; e += nt) Dn[e] = D[e];
+  for (int i = tid; i < na; i += nt) w[i] = 1.0;
+  __syncthreads();
+  const int nu = *nu_s, ncol = nu + mr;
+  for (int e = tid; e < nu * ncol; e += nt) {
+    const int k = e / ncol, c = e % ncol;
+    M[k * ldm + c] = c < nu ? A[U[k] + na * U[c]] : B[(c - nu) + mr * U[k]];
+    if (c == k) diag0[k] = A[U[k] + na * U[k]];
   }
-  wave_fence_sync();
-  // Each elimination step reads only values finished in earlier steps and writes
-  // different locations, so one wave synchronisation per step suffices.
+  __syncthreads();
   bool bad = false;
   for (int k = 0; k < nu; ++k) {
-    const double d = C[k * ldc + k];
-    if (!(d > kSpdRelTol * diag0[k])) {
+    const double piv = M[k * ldm + k];
+    if (!(piv > kSpdRelTol * diag0[k])) {  // same value in every thread: uniform exit
       bad = true;
       break;
     }
-    const double inv = 1.0 / sqrt(d);
-    if (lane == 0) Lf[k * ldc + k] = sqrt(d);
-    for (int i = k + 1 + lane; i < nu; i += kWave) Lf[i * ldc + k] = C[i * ldc + k] * inv;
-    const int rem = nu - k - 1;
-    const double inv2 = inv * inv;
-    for (int e = lane; e < rem * rem; e += kWave) {
-      const int i = k + 1 + e % rem, j = k + 1 + e / rem;
-      if (j <= i) C[i * ldc + j] -= C[i * ldc + k] * C[j * ldc + k] * inv2;
+    const double inv = 1.0 / piv;
+    const int rem = ncol - k - 1;  // columns right of k
+    for (int e = tid; e < nu * rem; e += nt) {
+      const int i = e / rem, c = k + 1 + e % rem;
+      if (i != k) M[i * ldm + c] -= M[i * ldm + k] * inv * M[k * ldm + c];
     }
-    wave_fence_sync();
+    __syncthreads();
   }
   if (!bad) {
-    // L Z = X: row k of Z is X[k] / L_kk once rows < k have been eliminated from X[k]
-    for (int k = 0; k < nu; ++k) {
-      const double inv = 1.0 / Lf[k * ldc + k];
-      for (int p = lane; p < mr; p += kWave) Z[k * ldx + p] = X[k * ldx + p] * inv;
-      for (int e = lane; e < (nu - k - 1) * mr; e += kWave) {
-        const int i = k + 1 + e / mr, p = e % mr;
-        X[i * ldx + p] -= Lf[i * ldc + k] * (X[k * ldx + p] * inv);
-      }
-      wave_fence_sync();
-    }
-    // L^T X = Z, from the last row up; the solution goes to X
-    for (int k = nu - 1; k >= 0; --k) {
-      const double inv = 1.0 / Lf[k * ldc + k];
-      for (int p = lane; p < mr; p += kWave) X[k * ldx + p] = Z[k * ldx + p] * inv;
-      for (int e = lane; e < k * mr; e += kWave) {
-        const int i = e / mr, p = e % mr;
-        Z[i * ldx + p] -= Lf[k * ldc + i] * (Z[k * ldx + p] * inv);
-      }
-      wave_fence_sync();
-    }
-  }
-  // new dictionary in LDS: solved atoms normalised (W), every other atom unchanged
-  for (int e = lane; e < mr * na; e += kWave) Dn[e] = D[e];
-  for (int i = lane; i < na; i += kWave) w[i] = 1.0;
-  wave_fence_sync();
-  if (!bad) {
-    for (int k = lane; k < nu; k += kWave) {
-      const int i = U[k];
+    // row k now reads [pivot_k e_k | pivot_k * (D*^T)_k]: normalise each solved atom
+    for (int k = tid; k < nu; k += nt) {
+      const double inv = 1.0 / M[k * ldm + k];
       double nrm = 0.0;
-      for (int p = 0; p < mr; ++p) nrm += X[k * ldx + p] * X[k * ldx + p];
+      for (int p = 0; p < mr; ++p) {
+        const double v = M[k * ldm + nu + p] * inv;
+        nrm += v * v;
+      }
       nrm = sqrt(nrm);
       if (nrm > 0.0) {
+        const int i = U[k];
         w[i] = nrm;
-        for (int p = 0; p < mr; ++p) Dn[p + mr * i] = X[k * ldx + p] / nrm;
+        for (int p = 0; p < mr; ++p) Dn[p + mr * i] = (M[k * ldm + nu + p] * inv) / nrm;
       }
     }
-  } else if (lane == 0) {
+  } else if (tid == 0) {
     atomicOr(status, kStatusSingular);
     atomicAdd(&counters[kCtrSingular], 1ull);
   }
-  wave_fence_sync();
-  // write back D, its compute-type copy and the Gram matrix D^T D (from LDS)
-  for (int e = lane; e < mr * na; e += kWave) {
+  __syncthreads();
+  for (int e = tid; e < mr * na; e += nt) {
     D[e] = Dn[e];
     Dc[e] = (T)Dn[e];
   }
-  for (int e = lane; e < na * na; e += kWave) {
+  for (int e = tid; e < na * na; e += nt) {
     const int i = e % na, j = e / na;
     double v = 0.0;
     for (int p = 0; p < mr; ++p) v += Dn[p + mr * i] * Dn[p + mr * j];
