@@ -40,13 +40,16 @@ struct MCfg {
   static constexpr int TI = N1 / 4, TJ = N2 / 4, NT = TI * TJ;  // 4x4 tiles
   static constexpr int M = M1 * M2;
   static constexpr int NL = S * (S + 1) / 2;
+  // LDS strides padded to odd word counts, so that the 16 signals of a wave (and the
+  // atoms they picked) fall into different banks
+  static constexpr int YS = M + 1, LD1 = M1 + 1, LD2 = M2 + 1, NLP = NL + 1;
   static constexpr int NAX = N1 > N2 ? N1 : N2, MRX = M1 > M2 ? M1 : M2;
   static constexpr int TPX = (NAX + 15) / 16, TRX = (MRX + 15) / 16, NPX = 16 * TPX + 1;
   static constexpr int SUB = 8;  // signals per epilogue pass
-  static constexpr int WORK = kSigs * NL > SUB * MRX * NPX ? kSigs * NL : SUB * MRX * NPX;
+  static constexpr int WORK = kSigs * NLP > SUB * MRX * NPX ? kSigs * NLP : SUB * MRX * NPX;
   static constexpr int NTILE = TPX * TPX + TRX * TPX;
   static constexpr int NENTX = NAX * NAX + MRX * NAX + 1;
-  static constexpr int STAGE = kSigs * M > NENTX ? kSigs * M : NENTX;
+  static constexpr int STAGE = kSigs * YS > NENTX ? kSigs * YS : NENTX;
   static_assert(N1 % 4 == 0 && N2 % 4 == 0, "4x4 tiles");
   static_assert(NT * 4 <= 64, "at most 64 correlations per lane (6-bit position in the keys)");
   static_assert(M % 4 == 0 && M2 % kLanes == 0, "staging and lane split of the first correlation");
@@ -82,9 +85,9 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
   __shared__ float sG2[N2 * N2];
   __shared__ __align__(16) float sG1P[N1 * N1];  // [ik][c][bi] = G1[4bi + c, ik]
   __shared__ __align__(16) float sG2P[N2 * N2];  // [jk][c][bj] = G2[jk, 4bj + c]
-  __shared__ __align__(16) float sD1[M1 * N1];
+  __shared__ __align__(16) float sD1[C::LD1 * N1];  // D1[p, i] at p + LD1 i
   __shared__ __align__(16) float sD1P[M1 * N1];  // [p][c][bi] = D1[p, 4bi + c]
-  __shared__ __align__(16) float sD2[M2 * N2];
+  __shared__ __align__(16) float sD2[C::LD2 * N2];  // D2[q, j] at q + LD2 j
   __shared__ __align__(16) float sY[kWaves][C::STAGE];
   __shared__ float sWork[kWaves][C::WORK];
   __shared__ float sAcc[kWaves][C::NTILE * 4 * kWave];
@@ -104,11 +107,11 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
     sG2P[e] = a.G2[jk + N2 * (4 * bj + cc)];
   }
   for (int e = tid; e < M1 * N1; e += blockDim.x) {
-    sD1[e] = a.D1[e];
+    sD1[e % M1 + C::LD1 * (e / M1)] = a.D1[e];
     const int p = e / N1, rem = e % N1, cc = rem / TI, bi = rem % TI;
     sD1P[e] = a.D1[p + M1 * (4 * bi + cc)];
   }
-  for (int e = tid; e < M2 * N2; e += blockDim.x) sD2[e] = a.D2[e];
+  for (int e = tid; e < M2 * N2; e += blockDim.x) sD2[e % M2 + C::LD2 * (e / M2)] = a.D2[e];
   __syncthreads();
 
   const float stop_rel = (float)a.stop_rel, dep_eps = (float)a.dep_eps, piv = (float)a.pivot_fp64;
@@ -118,6 +121,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
   const int eside = a.sums_side;
   const int ena = eside == 2 ? N2 : N1, emr = eside == 2 ? M2 : M1, emc = eside == 2 ? M1 : M2;
   const float* eDo = eside == 2 ? sD1 : sD2;
+  const int eld = eside == 2 ? C::LD1 : C::LD2;
   f32x4* acc = reinterpret_cast<f32x4*>(sAcc[wv]) + lane;
 #pragma unroll
   for (int q = 0; q < C::NTILE; ++q) acc[q * kWave] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -127,32 +131,30 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
     const int64_t k0 = grp * kSigs;
     const int nvalid = (int)((nsig - k0) < kSigs ? (nsig - k0) : kSigs);
     {
-      float4* dst = reinterpret_cast<float4*>(ys);
+      // signal b of the group at ys + b * YS
       const int nchunk = nvalid * M / 4;
-      if (!a.index) {
-        const float4* src = reinterpret_cast<const float4*>(a.Y + k0 * M);
-        for (int e = lane; e < kSigs * M / 4; e += kWave)
-          dst[e] = e < nchunk ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
-      } else {
-        for (int e = lane; e < kSigs * M / 4; e += kWave) {
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (e < nchunk) {
-            const int b = e / (M / 4), off = e % (M / 4);
-            v = reinterpret_cast<const float4*>(a.Y + (int64_t)a.index[k0 + b] * M)[off];
-          }
-          dst[e] = v;
-        }
+      for (int e = lane; e < kSigs * M / 4; e += kWave) {
+        const int b = e / (M / 4), off = e % (M / 4);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < nchunk)
+          v = a.index ? reinterpret_cast<const float4*>(a.Y + (int64_t)a.index[k0 + b] * M)[off]
+                      : reinterpret_cast<const float4*>(a.Y + k0 * M)[e];
+        float* d = ys + b * C::YS + 4 * off;
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
       }
     }
     wave_sync();
-    const float* y = ys + g * M;
+    const float* y = ys + g * C::YS;
     const bool valid = g < nvalid;
 
     // ---- ||Y|| and C = D1^T (Y D2) into the tile registers
     float yy = 0.f;
 #pragma unroll
     for (int u = 0; u < M / kLanes; ++u) {
-      const float v = y[c + kLanes * u];
+      const float v = y[c * (M / kLanes) + u];
       yy += v * v;
     }
     const float ynorm = sqrtf(quad_sum(yy));
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
       for (int q = 0; q < M2; ++q) {
         const float yv = y[p + M1 * q];
 #pragma unroll
-        for (int bj = 0; bj < TJ; ++bj) vb[bj] += yv * sD2[q + M2 * (4 * bj + c)];
+        for (int bj = 0; bj < TJ; ++bj) vb[bj] += yv * sD2[q + C::LD2 * (4 * bj + c)];
       }
       const float* d1p = sD1P + p * N1 + c * TI;  // D1[p, 4bi + c]
 #pragma unroll
@@ -182,7 +184,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
     }
 
     // ---- greedy loop
-    float* L = sWork[wv] + g * C::NL;
+    float* L = sWork[wv] + g * C::NLP;
     float dinv[S], x[S];
     int ia[S], ja[S];
 #pragma unroll
@@ -277,8 +279,8 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
           const int q = c + kLanes * u;
           float col = 0.f;
 #pragma unroll
-          for (int p = 0; p < M1; ++p) col += sD1[p + M1 * it] * y[p + M1 * q];
-          part += col * sD2[q + M2 * jt];
+          for (int p = 0; p < M1; ++p) col += sD1[p + C::LD1 * it] * y[p + M1 * q];
+          part += col * sD2[q + C::LD2 * jt];
         }
         cor = quad_sum(part);
 #pragma unroll
@@ -333,11 +335,11 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
     float rr = 0.f;
 #pragma unroll
     for (int u = 0; u < M / kLanes; ++u) {
-      const int e = c + kLanes * u;
+      const int e = c * (M / kLanes) + u;
       const int p = e % M1, q = e / M1;
       float r = y[e];
 #pragma unroll
-      for (int k = 0; k < S; ++k) r -= x[k] * sD1[p + M1 * ia[k]] * sD2[q + M2 * ja[k]];
+      for (int k = 0; k < S; ++k) r -= x[k] * sD1[p + C::LD1 * ia[k]] * sD2[q + C::LD2 * ja[k]];
       rr += r * r;
     }
     rr = quad_sum(rr);
@@ -377,7 +379,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
 #pragma unroll
             for (int t = 0; t < S; ++t) {
               const int ra = eside == 1 ? ia[t] : ja[t], rb = eside == 1 ? ja[t] : ia[t];
-              col[ra] += x[t] * eDo[cc + emc * rb];
+              col[ra] += x[t] * eDo[cc + eld * rb];
             }
           }
         }
@@ -391,7 +393,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
 #pragma unroll
           for (int i = 0; i < C::TRX; ++i) {
             const int row = 16 * i + r16;
-            ay[i] = row < emr ? (eside == 1 ? ys[b * M + cc * M1 + row] : ys[b * M + cc + M1 * row]) : 0.f;
+            ay[i] = row < emr ? (eside == 1 ? ys[b * C::YS + cc * M1 + row] : ys[b * C::YS + cc + M1 * row]) : 0.f;
           }
 #pragma unroll
           for (int i = 0; i < C::TPX; ++i)
