@@ -51,7 +51,18 @@ struct Ctx {
   hipStream_t side = nullptr;  // internal stream for graph replay (default priority)
   std::vector<hipEvent_t> ev;  // timing events
   hipEvent_t join_a = nullptr, join_b = nullptr;
+  // graph branches for the problems of one call (default priority, created on first use)
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> branch_join;
+  hipEvent_t fork = nullptr;
 };
+
+// Problems of one sdl_learn call run as parallel branches of the captured graph (at
+// most this many streams; problems beyond it share branches round-robin).
+constexpr int kMaxBranches = 8;
+// Algorithm 1 iterations captured per graph (replayed K / this times; the remainder
+// is launched directly).
+constexpr int kItersPerGraph = 4;
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Ctx*> g_ctx;
@@ -494,10 +505,10 @@ int run_code(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, 
 }
 
 template <typename T>
-int one_iteration(sdl_problem* p, int nprob, int K, const Opt& o, const Plan& pl, Launcher& L) {
-  for (int q = 0; q < nprob; ++q) {
+int iterate_problem(sdl_problem* p, int q, int K, const Opt& o, const Plan& pl, Launcher& L) {
+  {
     const sdl_problem& r = p[q];
-    if (r.N == 0) continue;
+    if (r.N == 0) return SDL_OK;
     const PBuf& b = pl.pb[q];
     if (o.proposer) {
       SDL_TRY(run_code<T>(r, b, o, pl, L));
@@ -524,6 +535,48 @@ int one_iteration(sdl_problem* p, int nprob, int K, const Opt& o, const Plan& pl
         SDL_TRY(run_update<T>(1, r, b, pl, false, L));
       }
     }
+  }
+  return SDL_OK;
+}
+
+// One Algorithm 1 iteration of every problem, in order on L's stream.
+template <typename T>
+int one_iteration(sdl_problem* p, int nprob, int K, const Opt& o, const Plan& pl, Launcher& L) {
+  for (int q = 0; q < nprob; ++q) SDL_TRY(iterate_problem<T>(p, q, K, o, pl, L));
+  return SDL_OK;
+}
+
+// The same while L's stream is being captured: the problems are independent (own
+// buffers; shared counters are updated atomically), so each gets a branch of the
+// graph, forked from and joined back into L's stream.
+template <typename T>
+int one_iteration_branched(sdl_problem* p, int nprob, int K, const Opt& o, const Plan& pl, Launcher& L, Ctx* ctx) {
+  int nact = 0;
+  for (int q = 0; q < nprob; ++q) nact += p[q].N > 0;
+  // a proposer's scratch buffers are shared by all problems: those run in order
+  if (nact <= 1 || o.proposer) return one_iteration<T>(p, nprob, K, o, pl, L);
+  const int nb = nact < kMaxBranches ? nact : kMaxBranches;
+  while ((int)ctx->branch.size() < nb) {
+    hipStream_t s;
+    hipEvent_t e;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->branch.push_back(s);
+    ctx->branch_join.push_back(e);
+  }
+  if (!ctx->fork) HIP_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ctx->fork, L.st));
+  for (int i = 0; i < nb; ++i) HIP_TRY(hipStreamWaitEvent(ctx->branch[i], ctx->fork, 0));
+  int slot = 0;
+  for (int q = 0; q < nprob; ++q) {
+    if (p[q].N == 0) continue;
+    Launcher B{ctx->branch[slot % nb], false, ctx, L.marks};
+    SDL_TRY(iterate_problem<T>(p, q, K, o, pl, B));
+    ++slot;
+  }
+  for (int i = 0; i < nb; ++i) {
+    HIP_TRY(hipEventRecord(ctx->branch_join[i], ctx->branch[i]));
+    HIP_TRY(hipStreamWaitEvent(L.st, ctx->branch_join[i], 0));
   }
   return SDL_OK;
 }
@@ -560,8 +613,10 @@ int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hi
     Launcher G{ctx->side, false, ctx, &marks};
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
+    const int per = K < kItersPerGraph ? K : kItersPerGraph;
     HIP_TRY(hipStreamBeginCapture(ctx->side, hipStreamCaptureModeRelaxed));
-    int rc = one_iteration<T>(p, nprob, K, o, pl, G);
+    int rc = SDL_OK;
+    for (int it = 0; it < per && rc == SDL_OK; ++it) rc = one_iteration_branched<T>(p, nprob, K, o, pl, G, ctx);
     hipError_t ce = hipStreamEndCapture(ctx->side, &g);
     if (rc != SDL_OK) {
       if (g) (void)hipGraphDestroy(g);
@@ -569,7 +624,8 @@ int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hi
     }
     HIP_TRY(ce);
     HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-    for (int it = 0; it < K; ++it) HIP_TRY(hipGraphLaunch(ge, ctx->side));
+    for (int it = 0; it + per <= K; it += per) HIP_TRY(hipGraphLaunch(ge, ctx->side));
+    for (int it = 0; it < K % per; ++it) SDL_TRY(one_iteration<T>(p, nprob, K, o, pl, G));
     HIP_TRY(hipEventRecord(ctx->join_b, ctx->side));
     HIP_TRY(hipStreamWaitEvent(st, ctx->join_b, 0));
     HIP_TRY(hipStreamSynchronize(st));

@@ -263,3 +263,67 @@ def test_timing_stats_filled(rng):
     d = st.as_dict()
     assert d["kernel_launches"]["sparse_code"] == 2 * 2 + 1
     assert d["kernel_ms"]["sparse_code"] > 0
+
+
+# ------------------------------------------------------------------ uneven multi-problem batch
+
+UNEVEN = [(8, 8, 16, 16, 6, 600), (12, 12, 20, 20, 10, 300), (16, 16, 32, 32, 16, 120), (32, 24, 48, 36, 20, 40)]
+
+
+def _uneven(rng):
+    out = []
+    for m1, m2, n1, n2, s, N in UNEVEN:
+        t1, t2 = rand_dicts(rng, m1, m2, n1, n2)
+        Y, _ = planted(rng, N, t1, t2, s, noise=0.03)
+        d1, d2 = rand_dicts(rng, m1, m2, n1, n2)
+        out.append((Y, d1, d2, s))
+    return out
+
+
+def test_uneven_batch_sparse_code_matches_oracle(rng):
+    """Four problems of different shapes in one call (the uneven batch): each coded as the oracle codes it."""
+    data = _uneven(rng)
+    probs = [api.Problem.from_math(Y, d1, d2, s, dtype=torch.float32, device=DEV) for Y, d1, d2, s in data]
+    api.sparse_code(probs)
+    torch.cuda.synchronize()
+    for (Y, d1, d2, s), pr in zip(data, probs):
+        so, co, _ = oracle.omp(Y, d1, d2, s)
+        agree, ties, bad, err = compare_codes(Y, d1, d2, pr.supp.cpu().numpy(), pr.coef.cpu().double().numpy(),
+                                              so, co, 1e-4, 1e-4)
+        print(Y.shape, "agree", agree, "ties", ties, "bad", bad, "err %.2e" % err)
+        assert agree >= 0.95 * len(Y) and bad <= max(1, len(Y) // 100) and err <= 2e-4
+
+
+@pytest.mark.parametrize("K", [3, 6])
+def test_uneven_batch_learn_equals_separate_calls(K, rng):
+    """Algorithm 1 on the uneven batch in one call (problems as parallel graph branches, several
+    iterations per graph) gives bit for bit what one call per problem gives, and each problem's
+    RMSE trace stays within 1% of the FP64 oracle's."""
+    data = _uneven(rng)
+    together = [api.Problem.from_math(Y, d1, d2, s, dtype=torch.float32, device=DEV) for Y, d1, d2, s in data]
+    tr_all = api.learn(together, K)
+    for q, (Y, d1, d2, s) in enumerate(data):
+        alone = api.Problem.from_math(Y, d1, d2, s, dtype=torch.float32, device=DEV)
+        tr = api.learn(alone, K)[0]
+        np.testing.assert_array_equal(tr_all[q], tr)
+        np.testing.assert_array_equal(together[q].d1(), alone.d1())
+        np.testing.assert_array_equal(together[q].d2(), alone.d2())
+        np.testing.assert_array_equal(together[q].supp.cpu().numpy(), alone.supp.cpu().numpy())
+        if K == 3:
+            ref = oracle.learn(Y, d1, d2, s, K, p=8)
+            np.testing.assert_allclose(tr, ref["rmse"], rtol=0.01)
+
+
+def test_learn_graph_remainder_iterations_equal_eager(rng):
+    """K not a multiple of the iterations captured per graph: replays plus direct launches equal eager."""
+    m1, m2, n1, n2, s, N = 8, 8, 16, 16, 8, 3000
+    t1, t2 = rand_dicts(rng, m1, m2, n1, n2)
+    Y, _ = planted(rng, N, t1, t2, s, noise=0.05)
+    d1, d2 = rand_dicts(rng, m1, m2, n1, n2)
+    outs = []
+    for use_graph in (0, 1):
+        pr = api.Problem.from_math(Y, d1, d2, s, dtype=torch.float32, device=DEV)
+        tr = api.learn(pr, 7, use_graph=use_graph)
+        outs.append((tr, pr.d1(), pr.d2(), pr.coef.cpu().numpy()))
+    for u, v in zip(*outs):
+        np.testing.assert_array_equal(u, v)
