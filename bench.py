@@ -229,6 +229,12 @@ def main():
                "sample": "first %d signals of the workload, %d Algorithm-1 iterations plus the final 2D-OMP, "
                          "FP64 oracle, %d threads" % (ns, args.cpu_iters, p)}
 
+    # measured ceilings of this device (copy kernel, FMA and MFMA chains)
+    measured = {"hbm_copy_gbs": api.probe_hbm_copy(1 << 30, reps=5)}
+    for k in api.PROBE_KINDS:
+        measured[k + "_tflops"] = api.probe_peak(k, reps=5)
+    peak_meas = measured["fp32_mfma_4x4x1_tflops" if tuned and tuned[3] else "fp32_fma_tflops"]
+
     learned = None
     if not args.no_learned and dtype == torch.float32:
         learned = learned_vs_plain(args, api, oracle, synth)
@@ -257,7 +263,9 @@ def main():
                      "peak": FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6, "unit": "TFLOP/s",
                      "frac": achieved_tflops / (FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6),
                      "traffic": measured_traffic(w, symbol), "traffic_unit": "bytes/launch",
-                     "avg_ms": omp_ms, "flops_per_launch": flops},
+                     "avg_ms": omp_ms, "flops_per_launch": flops,
+                     "peak_measured": peak_meas, "frac_measured": achieved_tflops / peak_meas},
+        "measured_peaks": measured,
         "kernel_avg_ms": per_class,
         "rmse_final": float(trace[-1]),
         "rmse_vs_oracle": rmse_ratio,

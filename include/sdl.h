@@ -204,6 +204,19 @@ int sdl_learned_sparse_code(sdl_proposer* p, const sdl_problem* prob, int32_t np
 int sdl_proposer_calibrate(sdl_proposer* p, const sdl_problem* prob, double violation, double* tau_out,
                            void* stream);
 
+/* Measurement aids (no counterpart in the paper): achievable ceilings of the current
+ * device, for quoting kernel fractions against measured as well as published peaks.
+ * sdl_probe_hbm_copy copies bytes (rounded down to a multiple of 16) from src to dst
+ * (device pointers, not overlapping, each at least `bytes` long) reps times with a
+ * grid-stride kernel and stores the best rate, read plus write bytes, in *gbs (1e9 B/s).
+ * sdl_probe_peak runs independent arithmetic chains on every SIMD and stores the best of
+ * reps launches in *tflops: kind 0 = FP32 FMA on the vector ALUs (unpacked), 1 = FP32
+ * MFMA 16x16x4, 2 = FP32 MFMA 4x4x1 (16 blocks), 3 = FP64 FMA.  sink: device, >= 8 bytes,
+ * written only if a chain reaches a value it cannot reach.  Both synchronise the stream;
+ * SDL_E_INVAL for NULL pointers, bytes < 16, reps < 1 or an unknown kind. */
+int sdl_probe_hbm_copy(void* dst, const void* src, size_t bytes, int32_t reps, double* gbs, void* stream);
+int sdl_probe_peak(int32_t kind, void* sink, int32_t reps, double* tflops, void* stream);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* sdl_last_error(void);
 

@@ -91,6 +91,10 @@ def lib():
         L.sdl_proposer_logits.argtypes = [vp, vp, i64, vp, vp]
         L.sdl_learned_sparse_code.argtypes = [vp, P, i32, vp, ctypes.POINTER(Options), vp]
         L.sdl_proposer_calibrate.argtypes = [vp, P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+        L.sdl_probe_hbm_copy.argtypes = [vp, vp, ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_double), vp]
+        L.sdl_probe_hbm_copy.restype = ctypes.c_int
+        L.sdl_probe_peak.argtypes = [i32, vp, i32, ctypes.POINTER(ctypes.c_double), vp]
+        L.sdl_probe_peak.restype = ctypes.c_int
         for f in (L.sdl_proposer_create, L.sdl_proposer_get_params, L.sdl_proposer_set_params,
                   L.sdl_proposer_gradient, L.sdl_proposer_train, L.sdl_proposer_logits, L.sdl_learned_sparse_code,
                   L.sdl_proposer_calibrate):

@@ -259,3 +259,25 @@ def learned_sparse_code(proposer: Proposer, problems, tau: float, accept: torch.
 
 def new_stats() -> _native.Stats:
     return _native.Stats()
+
+
+PROBE_KINDS = {"fp32_fma": 0, "fp32_mfma_16x16x4": 1, "fp32_mfma_4x4x1": 2, "fp64_fma": 3}
+
+
+def probe_hbm_copy(nbytes: int = 1 << 30, reps: int = 5, stream=None) -> float:
+    """Best device copy rate, read + write bytes, in GB/s (buffers allocated here)."""
+    src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    gbs = ctypes.c_double()
+    _native.check(_native.lib().sdl_probe_hbm_copy(dst.data_ptr(), src.data_ptr(), nbytes, reps, ctypes.byref(gbs),
+                                                   _stream(stream)))
+    return gbs.value
+
+
+def probe_peak(kind: str, reps: int = 5, stream=None) -> float:
+    """Achievable arithmetic peak in TFLOP/s; kind in PROBE_KINDS."""
+    sink = torch.zeros(2, dtype=torch.float64, device="cuda")
+    tf = ctypes.c_double()
+    _native.check(_native.lib().sdl_probe_peak(PROBE_KINDS[kind], sink.data_ptr(), reps, ctypes.byref(tf),
+                                               _stream(stream)))
+    return tf.value

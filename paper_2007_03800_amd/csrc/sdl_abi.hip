@@ -733,6 +733,23 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
   return SDL_OK;
 }
 
+int sdl_probe_hbm_copy(void* dst, const void* src, size_t bytes, int32_t reps, double* gbs, void* stream) {
+  g_err.clear();
+  if (!dst || !src || !gbs) return fail(SDL_E_INVAL, "NULL argument");
+  if (bytes < 16 || reps < 1) return fail(SDL_E_INVAL, "need bytes >= 16 and reps >= 1");
+  HIP_TRY(probe_hbm_copy(dst, src, bytes, reps, (hipStream_t)stream, gbs));
+  return SDL_OK;
+}
+
+int sdl_probe_peak(int32_t kind, void* sink, int32_t reps, double* tflops, void* stream) {
+  g_err.clear();
+  if (!sink || !tflops) return fail(SDL_E_INVAL, "NULL argument");
+  if (kind < 0 || kind > 3) return fail(SDL_E_INVAL, "kind = %d (0..3)", kind);
+  if (reps < 1) return fail(SDL_E_INVAL, "reps = %d < 1", reps);
+  HIP_TRY(probe_peak(kind, (float*)sink, reps, (hipStream_t)stream, tflops));
+  return SDL_OK;
+}
+
 int sdl_tuned_config(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* lanes_row,
                      int32_t* lanes_col, int32_t* waves_per_simd, int32_t* matrix_core, double* ms) {
   int lr = 0, lc = 0, wpe = 0, mf = 0;

@@ -120,6 +120,10 @@ hipError_t launch_tmod_solve(const double* src, int nrow, int ld, double* sums, 
                              double* G64, T* Gc, double* w, int* status, unsigned long long* counters,
                              const RmseOut& r, hipStream_t st);
 hipError_t tmod_solve_init_device();
+// Measurement aids (probe.hip): best copy rate (read + write, GB/s) and arithmetic peaks
+// (kind 0 FP32 FMA, 1 FP32 MFMA 16x16x4, 2 FP32 MFMA 4x4x1, 3 FP64 FMA; TFLOP/s).
+hipError_t probe_hbm_copy(void* dst, const void* src, size_t bytes, int reps, hipStream_t st, double* gbs);
+hipError_t probe_peak(int kind, float* sink, int reps, hipStream_t st, double* tflops);
 template <typename T>
 hipError_t launch_dict_prep(const double* D, int mr, int na, T* Dc, double* G64, T* Gc, hipStream_t st);
 template <typename T>

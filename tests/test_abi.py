@@ -82,3 +82,14 @@ def test_default_options():
     o = _native.default_options()
     assert o.prec == 0 and o.use_graph == 1 and o.schedule == 0
     assert o.stop_rel < 0 and o.dep_eps < 0 and o.pivot_fp64 < 0
+
+
+def test_probe_validation():
+    lib = _native.lib()
+    d = ctypes.c_double()
+    assert lib.sdl_probe_hbm_copy(None, None, 1024, 1, ctypes.byref(d), None) == -1
+    assert lib.sdl_probe_hbm_copy(1, 2, 8, 1, ctypes.byref(d), None) == -1
+    assert lib.sdl_probe_hbm_copy(1, 2, 1024, 0, ctypes.byref(d), None) == -1
+    assert lib.sdl_probe_peak(4, 1, 1, ctypes.byref(d), None) == -1
+    assert lib.sdl_probe_peak(0, None, 1, ctypes.byref(d), None) == -1
+    assert lib.sdl_probe_peak(0, 1, 0, ctypes.byref(d), None) == -1
