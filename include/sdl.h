@@ -14,7 +14,11 @@
  *   atom index a = i + n1*j, the column of D2 (x) D1 that multiplies vec X_k
  *   supp[k*s + t]: t-th atom chosen for signal k (selection order), -1 = unused slot
  *   coef[k*s + t]: its coefficient, 0 in unused slots
- * Element type of Y, coef and res2: double for SDL_FP64, float for SDL_FP32.
+ * Element type of Y, coef and res2: double for SDL_FP64, float for SDL_FP32; for
+ * SDL_BF16 (mixed precision) Y holds bfloat16 values (16-bit patterns equal to the upper
+ * half of the FP32 encoding) and coef/res2 are float: signals are widened to FP32
+ * exactly where they are loaded, the sparse coding and the sums run in FP32, the
+ * dictionary solves in FP64 as for the other precisions.
  *
  * Pointers: every array pointer is a DEVICE pointer (HIP global memory) unless
  * marked "host".  The caller allocates and owns all of them and keeps them alive
@@ -39,9 +43,9 @@
 extern "C" {
 #endif
 
-#define SDL_ABI_VERSION 2
+#define SDL_ABI_VERSION 3
 
-typedef enum { SDL_FP64 = 0, SDL_FP32 = 1 } sdl_prec;
+typedef enum { SDL_FP64 = 0, SDL_FP32 = 1, SDL_BF16 = 2 } sdl_prec;
 
 enum {
   SDL_OK = 0,

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsdl.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "sdl.h")
 
-SDL_FP64, SDL_FP32 = 0, 1
+SDL_FP64, SDL_FP32, SDL_BF16 = 0, 1, 2
 STATUS = {0: "SDL_OK", -1: "SDL_E_INVAL", -2: "SDL_E_SHAPE", -3: "SDL_E_DEVICE", -4: "SDL_E_NOMEM",
           -5: "SDL_E_SINGULAR", -6: "SDL_E_NONFINITE", -7: "SDL_E_UNSUPPORTED"}
 KERNEL_CLASSES = ["sparse_code", "tmod_sums", "reduce", "solve", "prep", "rmse", "rescale", "spare"]

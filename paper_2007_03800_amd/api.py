@@ -20,7 +20,7 @@ import torch
 
 from . import _native
 
-_DT = {torch.float64: _native.SDL_FP64, torch.float32: _native.SDL_FP32}
+_DT = {torch.float64: _native.SDL_FP64, torch.float32: _native.SDL_FP32, torch.bfloat16: _native.SDL_BF16}
 
 
 class Problem:
@@ -36,7 +36,7 @@ class Problem:
         if D1.shape[1] != self.m1 or D2.shape[1] != self.m2:
             raise ValueError("dictionary row counts do not match the signal shape")
         if Y.dtype not in _DT:
-            raise ValueError("Y must be float32 or float64")
+            raise ValueError("Y must be float64, float32 or bfloat16")
         for t in (Y, D1, D2):
             if not t.is_contiguous():
                 raise ValueError("tensors must be contiguous (ABI layout)")
@@ -44,11 +44,12 @@ class Problem:
             raise ValueError("dictionaries are FP64 master copies")
         self.s = int(s)
         dev = Y.device
+        cdt = torch.float32 if Y.dtype == torch.bfloat16 else Y.dtype  # codes of BF16 signals are FP32
         self.Y, self.D1, self.D2 = Y, D1, D2
         self.supp = supp if supp is not None else torch.empty((self.N, self.s), dtype=torch.int32, device=dev)
-        self.coef = coef if coef is not None else torch.empty((self.N, self.s), dtype=Y.dtype, device=dev)
+        self.coef = coef if coef is not None else torch.empty((self.N, self.s), dtype=cdt, device=dev)
         self.res2 = res2 if res2 is not None else (
-            torch.empty(self.N, dtype=Y.dtype, device=dev) if with_res2 else None)
+            torch.empty(self.N, dtype=cdt, device=dev) if with_res2 else None)
 
     @classmethod
     def from_math(cls, Y, D1, D2, s, dtype=torch.float32, device="cuda"):

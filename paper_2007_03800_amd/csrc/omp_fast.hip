@@ -140,19 +140,14 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
     {
       float4* dst = reinterpret_cast<float4*>(ys);
       const int nchunk = nvalid * M / 4;
-      if (!a.index) {
-        const float4* src = reinterpret_cast<const float4*>(a.Y + k0 * M);
-        for (int e = lane; e < SPW * M / 4; e += kWave)
-          dst[e] = e < nchunk ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
-      } else {
-        for (int e = lane; e < SPW * M / 4; e += kWave) {
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (e < nchunk) {
-            const int b = e / (M / 4), off = e % (M / 4);
-            v = reinterpret_cast<const float4*>(a.Y + (int64_t)a.index[k0 + b] * M)[off];
-          }
-          dst[e] = v;
+      for (int e = lane; e < SPW * M / 4; e += kWave) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < nchunk) {
+          const int b = e / (M / 4), off = e % (M / 4);
+          const int64_t k = a.index ? (int64_t)a.index[k0 + b] : k0 + b;
+          v = load_signal4(a, k * M + 4 * off);
         }
+        dst[e] = v;
       }
     }
     wave_sync();

@@ -101,10 +101,9 @@ __global__ void __launch_bounds__(kWave) omp_generic_kernel(OmpArgs<T> a) {
 
   for (int64_t k = blockIdx.x; k < a.N; k += gridDim.x) {
     __syncthreads();
-    const T* Yk = a.Y + k * M;
     T yy = 0;
     for (int e = lane; e < M; e += kWave) {
-      T v = Yk[e];
+      const T v = a.Yh ? (T)bf16_to_float(a.Yh[k * M + e]) : a.Y[k * M + e];
       ys[e] = v;
       yy += v * v;
     }

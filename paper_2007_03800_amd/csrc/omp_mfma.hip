@@ -136,9 +136,10 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
       for (int e = lane; e < kSigs * M / 4; e += kWave) {
         const int b = e / (M / 4), off = e % (M / 4);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (e < nchunk)
-          v = a.index ? reinterpret_cast<const float4*>(a.Y + (int64_t)a.index[k0 + b] * M)[off]
-                      : reinterpret_cast<const float4*>(a.Y + k0 * M)[e];
+        if (e < nchunk) {
+          const int64_t k = a.index ? (int64_t)a.index[k0 + b] : k0 + b;
+          v = load_signal4(a, k * M + 4 * off);
+        }
         float* d = ys + b * C::YS + 4 * off;
         d[0] = v.x;
         d[1] = v.y;

@@ -154,7 +154,8 @@ Opt resolve(const sdl_options* o) {
 int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_in) {
   if (nprob < 0) return fail(SDL_E_INVAL, "nprob = %d < 0", nprob);
   if (nprob > 0 && !p) return fail(SDL_E_INVAL, "problem array is NULL");
-  if (o.prec != SDL_FP64 && o.prec != SDL_FP32) return fail(SDL_E_INVAL, "prec = %d is not an sdl_prec", o.prec);
+  if (o.prec != SDL_FP64 && o.prec != SDL_FP32 && o.prec != SDL_BF16)
+    return fail(SDL_E_INVAL, "prec = %d is not an sdl_prec", o.prec);
   if (o.schedule != 0 && o.schedule != 1) return fail(SDL_E_INVAL, "schedule = %d (0 or 1)", o.schedule);
   if (o.kernel < 0 || o.kernel > 2) return fail(SDL_E_INVAL, "kernel = %d (0, 1 or 2)", o.kernel);
   const size_t elem = o.prec == SDL_FP64 ? 8 : 4;
@@ -202,6 +203,7 @@ struct Plan {
   int* status;
   unsigned long long* counters;
   int* iter;     // per-problem RMSE counters
+  bool ybf16 = false;  // signals are bfloat16 (SDL_BF16)
   double* trace; // device trace
   size_t bytes;
 };
@@ -279,6 +281,11 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
   OmpArgs<T> a;
   a.m1 = r.m1; a.m2 = r.m2; a.n1 = r.n1; a.n2 = r.n2; a.s = r.s; a.N = r.N;
   a.Y = (const T*)r.Y;
+  a.Yh = nullptr;
+  if (pl.ybf16) {
+    a.Yh = (const uint16_t*)r.Y;
+    a.Y = nullptr;
+  }
   a.D1 = (const T*)b.Dc1;
   a.D2 = (const T*)b.Dc2;
   a.G1 = (const T*)b.G1c;
@@ -361,7 +368,8 @@ int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bo
   TmodArgs<T> a;
   a.side = side;
   a.m1 = r.m1; a.m2 = r.m2; a.n1 = r.n1; a.n2 = r.n2; a.s = r.s; a.N = r.N;
-  a.Y = (const T*)r.Y;
+  a.Y = pl.ybf16 ? nullptr : (const T*)r.Y;
+  a.Yh = pl.ybf16 ? (const uint16_t*)r.Y : nullptr;
   a.Dother = (const T*)(side == 1 ? b.Dc2 : b.Dc1);
   a.supp = r.supp;
   a.coef = (const T*)r.coef;
@@ -397,7 +405,10 @@ int begin_call(hipStream_t st, Ctx* ctx, const Plan& pl, int nprob) {
 template <typename T>
 int run_check_finite(const sdl_problem* p, int nprob, const Plan& pl, hipStream_t st) {
   for (int q = 0; q < nprob; ++q) {
-    HIP_TRY(launch_check_finite<T>((const T*)p[q].Y, p[q].N * p[q].m1 * p[q].m2, pl.status, st));
+    if (pl.ybf16)
+      HIP_TRY(launch_check_finite_bf16((const uint16_t*)p[q].Y, p[q].N * p[q].m1 * p[q].m2, pl.status, st));
+    else
+      HIP_TRY(launch_check_finite<T>((const T*)p[q].Y, p[q].N * p[q].m1 * p[q].m2, pl.status, st));
     HIP_TRY(launch_check_finite<double>(p[q].D1, (int64_t)p[q].m1 * p[q].n1, pl.status, st));
     HIP_TRY(launch_check_finite<double>(p[q].D2, (int64_t)p[q].m2 * p[q].n2, pl.status, st));
   }
@@ -439,6 +450,7 @@ int sparse_code_impl(const sdl_problem* p, int nprob, const Opt& o, hipStream_t 
   layout(p, nprob, sizeof(T), 0, nullptr, &pl);
   SDL_TRY(ensure_ws(ctx, pl.bytes, st));
   layout(p, nprob, sizeof(T), 0, ctx->ws, &pl);
+  pl.ybf16 = o.prec == SDL_BF16;
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, o.timing != 0 && o.stats != nullptr, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));
@@ -462,6 +474,7 @@ int tmod_update_impl(sdl_problem* p, int nprob, uint32_t sides, const Opt& o, hi
   layout(p, nprob, sizeof(T), 0, nullptr, &pl);
   SDL_TRY(ensure_ws(ctx, pl.bytes, st));
   layout(p, nprob, sizeof(T), 0, ctx->ws, &pl);
+  pl.ybf16 = o.prec == SDL_BF16;
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, o.timing != 0 && o.stats != nullptr, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));
@@ -592,6 +605,7 @@ int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hi
   layout(p, nprob, sizeof(T), K, nullptr, &pl);
   SDL_TRY(ensure_ws(ctx, pl.bytes, st));
   layout(p, nprob, sizeof(T), K, ctx->ws, &pl);
+  pl.ybf16 = o.prec == SDL_BF16;
   std::vector<std::pair<int, int>> marks;
   const bool timing = o.timing != 0 && o.stats != nullptr;
   Launcher L{st, timing, ctx, &marks};
@@ -705,9 +719,9 @@ int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, cons
 int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_options* o, void* stream) {
   g_err.clear();
   Opt opt = resolve(o);
-  opt.prec = SDL_FP32;
   SDL_TRY(validate(p, nprob, opt, false));
   if (reps < 1) return fail(SDL_E_INVAL, "reps = %d < 1", reps);
+  if (opt.prec == SDL_FP64) return SDL_OK;  // the register-resident kernels are FP32
   hipStream_t st = (hipStream_t)stream;
   Ctx* ctx;
   SDL_TRY(get_ctx(st, &ctx));
@@ -715,6 +729,7 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
   layout(p, nprob, sizeof(float), 0, nullptr, &pl);
   SDL_TRY(ensure_ws(ctx, pl.bytes, st));
   layout(p, nprob, sizeof(float), 0, ctx->ws, &pl);
+  pl.ybf16 = opt.prec == SDL_BF16;
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, false, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));
@@ -805,6 +820,7 @@ int sdl_learned_sparse_code(sdl_proposer* P, const sdl_problem* p, int32_t nprob
   layout(p, nprob, sizeof(float), 0, nullptr, &pl);
   SDL_TRY(ensure_ws(ctx, pl.bytes, st));
   layout(p, nprob, sizeof(float), 0, ctx->ws, &pl);
+  pl.ybf16 = opt.prec == SDL_BF16;
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, false, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));

@@ -23,6 +23,7 @@ struct OmpArgs {
   int m1, m2, n1, n2, s;
   int64_t N;
   const T* Y;
+  const uint16_t* Yh;  // non-null: the signals are bfloat16 (Y unused), widened to FP32 on load
   const T* D1;  // m1 x n1 column-major, in the compute type
   const T* D2;  // m2 x n2
   const T* G1;  // n1 x n1 = D1^T D1
@@ -50,10 +51,25 @@ struct TmodArgs {
   int m1, m2, n1, n2, s;
   int64_t N;
   const T* Y;
+  const uint16_t* Yh;  // non-null: the signals are bfloat16 (Y unused), widened to FP32 on load
   const T* Dother;  // compute-type copy of the dictionary that stays fixed
   const int32_t* supp;
   const T* coef;
 };
+
+// bfloat16 bit pattern -> FP32 (exact: the pattern is the upper half of the FP32 encoding)
+__device__ inline float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Four consecutive signal values starting at element off (a multiple of 4) as FP32:
+// one 16-byte load of FP32 signals, or one 8-byte load of bfloat16 signals.
+__device__ inline float4 load_signal4(const OmpArgs<float>& a, int64_t off) {
+  if (a.Yh) {
+    const uint2 h = *reinterpret_cast<const uint2*>(a.Yh + off);
+    return make_float4(bf16_to_float((uint16_t)(h.x & 0xFFFFu)), bf16_to_float((uint16_t)(h.x >> 16)),
+                       bf16_to_float((uint16_t)(h.y & 0xFFFFu)), bf16_to_float((uint16_t)(h.y >> 16)));
+  }
+  return *reinterpret_cast<const float4*>(a.Y + off);
+}
 
 // ---- launchers (defined in the .hip files) ----
 template <typename T>
@@ -135,6 +151,7 @@ hipError_t launch_rmse(const T* res2, int64_t N, double denom, double* part, int
                        int stride, int offset, int* counter, hipStream_t st);
 template <typename T>
 hipError_t launch_check_finite(const T* x, int64_t n, int* status, hipStream_t st);
+hipError_t launch_check_finite_bf16(const uint16_t* x, int64_t n, int* status, hipStream_t st);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
 
 }  // namespace sdl

@@ -118,6 +118,15 @@ __global__ void check_finite_kernel(const T* x, int64_t n, int* status) {
   }
 }
 
+__global__ void check_finite_bf16_kernel(const uint16_t* x, int64_t n, int* status) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    if ((x[e] & 0x7F80u) == 0x7F80u) {  // exponent all ones: infinity or NaN
+      atomicOr(status, kStatusNonfinite);
+      return;
+    }
+  }
+}
+
 __global__ void fill_int_kernel(int* p, int n, int v) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;
@@ -196,6 +205,14 @@ hipError_t launch_check_finite(const T* x, int64_t n, int* status, hipStream_t s
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(check_finite_kernel<T>, dim3((unsigned)g), dim3(256), 0, st, x, n, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite_bf16(const uint16_t* x, int64_t n, int* status, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(check_finite_bf16_kernel, dim3((unsigned)g), dim3(256), 0, st, x, n, status);
   return hipGetLastError();
 }
 

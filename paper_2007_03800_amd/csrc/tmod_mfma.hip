@@ -109,11 +109,10 @@ __global__ void __launch_bounds__(kWave* kWaves) tmod_sums_kernel(TmodArgs<T> a,
           const int ra = side == 1 ? i : j, rb = side == 1 ? j : i;
           tcol[ra] += cval[b * s + t] * Do[c + mc * rb];
         }
-        const T* Yb = a.Y + (kb + b) * M;
-        if (side == 1) {
-          for (int r = 0; r < mr; ++r) ycol[r] = Yb[r + a.m1 * c];  // column c of Y_b
-        } else {
-          for (int r = 0; r < mr; ++r) ycol[r] = Yb[c + a.m1 * r];  // row c of Y_b
+        const int64_t yb = (kb + b) * M;
+        for (int r = 0; r < mr; ++r) {
+          const int64_t e = yb + (side == 1 ? r + a.m1 * c : c + a.m1 * r);  // column / row c of Y_b
+          ycol[r] = a.Yh ? (T)bf16_to_float(a.Yh[e]) : a.Y[e];
         }
         for (int r = mr; r < MP; ++r) ycol[r] = T(0);
       } else {

@@ -1,0 +1,91 @@
+"""Mixed precision (signals stored in bfloat16, FP32 arithmetic, FP64 dictionary solves).
+
+Widening a bfloat16 value to FP32 is exact, so a BF16 problem must give bit for bit what
+the FP32 path gives on the same rounded signals; and on the mixed-precision workload
+(12x12 signals, 24x24 atoms, s = 12) the codes and the learning trace follow the FP64
+oracle run on those rounded signals (same bars as FP32: supports agree except near-ties,
+coefficients within 1e-4 relative, RMSE within 1%)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2007_03800_amd import api, synth
+from paper_2007_03800_amd._native import SdlError
+from tests.conftest import planted, rand_dicts
+from tests.gpu_helpers import compare_codes
+
+pytestmark = pytest.mark.gpu
+
+
+def rounded(Y):
+    """bfloat16 rounding (nearest, ties to even) done by torch on the host, back in FP64."""
+    return torch.as_tensor(Y).to(torch.bfloat16).double().numpy()
+
+
+def pair(Y, d1, d2, s):
+    Yr = rounded(Y)
+    b = api.Problem.from_math(Yr, d1, d2, s, dtype=torch.bfloat16)
+    f = api.Problem.from_math(Yr, d1, d2, s, dtype=torch.float32)
+    assert torch.equal(b.Y.float(), f.Y)
+    return Yr, b, f
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 24, 24, 12, 700), (8, 8, 16, 16, 8, 900), (5, 9, 11, 6, 7, 130)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_sparse_code_bf16_equals_fp32_on_rounded_signals(shape, rng):
+    m1, m2, n1, n2, s, N = shape
+    t1, t2 = rand_dicts(rng, m1, m2, n1, n2)
+    Y, _ = planted(rng, N, t1, t2, s, noise=0.03)
+    _, b, f = pair(Y, t1, t2, s)
+    api.sparse_code(b)
+    api.sparse_code(f)
+    torch.cuda.synchronize()
+    assert b.coef.dtype == torch.float32 and b.res2.dtype == torch.float32
+    assert torch.equal(b.supp, f.supp) and torch.equal(b.coef, f.coef) and torch.equal(b.res2, f.res2)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_learn_bf16_equals_fp32_on_rounded_signals(schedule, rng):
+    m1, m2, n1, n2, s, N = 12, 12, 24, 24, 12, 1500
+    t1, t2 = rand_dicts(rng, m1, m2, n1, n2)
+    Y, _ = planted(rng, N, t1, t2, s, noise=0.05)
+    d1, d2 = rand_dicts(rng, m1, m2, n1, n2)
+    _, b, f = pair(Y, d1, d2, s)
+    tb = api.learn(b, 3, schedule=schedule)
+    tf = api.learn(f, 3, schedule=schedule)
+    np.testing.assert_array_equal(tb, tf)
+    np.testing.assert_array_equal(b.d1(), f.d1())
+    np.testing.assert_array_equal(b.d2(), f.d2())
+    assert torch.equal(b.coef, f.coef)
+
+
+def test_mixed_workload_matches_oracle_on_rounded_signals():
+    w = synth.WORKLOADS["mixed_12x12_n24_s12"]
+    Y = rounded(synth.signals(w, 0, 3000))
+    d1, d2 = synth.true_dictionaries(w)
+    pr = api.Problem.from_math(Y, d1, d2, w.s, dtype=torch.bfloat16)
+    api.sparse_code(pr)
+    torch.cuda.synchronize()
+    so, co, _ = oracle.omp(Y, d1, d2, w.s, p=8)
+    agree, ties, bad, err = compare_codes(Y, d1, d2, pr.supp.cpu().numpy(), pr.coef.cpu().double().numpy(), so, co,
+                                          1e-4, 1e-4)
+    print("agree", agree, "ties", ties, "bad", bad, "err %.2e" % err)
+    assert agree >= 0.97 * len(Y) and bad <= 3 and err <= 2e-4
+    e1, e2 = synth.initial_dictionaries(w)
+    K = 3
+    ref = oracle.learn(Y, e1, e2, w.s, K, p=8)
+    pr = api.Problem.from_math(Y, e1, e2, w.s, dtype=torch.bfloat16)
+    tr = api.learn(pr, K)[0]
+    print("rmse gpu", tr, "oracle", ref["rmse"])
+    np.testing.assert_allclose(tr, ref["rmse"], rtol=0.01)
+
+
+def test_nonfinite_bf16_input_reported(rng):
+    d1, d2 = rand_dicts(rng, 8, 8, 12, 12)
+    Y = rng.standard_normal((50, 8, 8))
+    Y[9, 1, 4] = np.inf
+    pr = api.Problem.from_math(Y, d1, d2, 4, dtype=torch.bfloat16)
+    with pytest.raises(SdlError) as e:
+        api.sparse_code(pr, check_finite=1)
+    assert e.value.status == -6
