@@ -133,6 +133,89 @@ def learned_vs_plain(args, api, oracle, synth):
     return out
 
 
+def device_signals(synth, w, dtype, k0=0, k1=None, chunk=100_000):
+    """Signals k0..k1 of workload w, generated in chunks straight into a device tensor
+    in the ABI layout (each signal column-major)."""
+    import torch
+    k1 = w.N if k1 is None else k1
+    Y = torch.empty((k1 - k0, w.m2, w.m1), dtype=dtype, device="cuda")
+    for c0 in range(k0, k1, chunk):
+        c1 = min(k1, c0 + chunk)
+        Y[c0 - k0:c1 - k0] = torch.from_numpy(synth.signals(w, c0, c1, layout="colmajor")).to("cuda", dtype)
+    return Y
+
+
+def timed_learn(api, fresh, K):
+    """Autotune, one warm-up iteration, then K graph-replayed iterations of Algorithm 1 from
+    fresh problems; returns (problems, trace, seconds)."""
+    import torch
+    api.autotune(fresh(), reps=3)
+    api.learn(fresh(), 1)
+    probs = fresh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trace = api.learn(probs, K)
+    torch.cuda.synchronize()
+    return probs, trace, time.perf_counter() - t0
+
+
+def kernel_name(api, w):
+    t = api.tuned_config(w.m1, w.m2, w.n1, w.n2, w.s)
+    if t is None:
+        return "generic (one wave per signal)"
+    return "register-resident lanes %dx%d, %d waves/SIMD%s" % (t[0], t[1], t[2], ", refresh on MFMA" if t[3] else "")
+
+
+def mixed_workload(api, oracle, synth):
+    """Mixed precision at its own shape: 1M signals of 12x12 stored in bfloat16, 24x24 atoms,
+    s = 12, K = 10 iterations from the random initial dictionaries."""
+    import torch
+    w = synth.WORKLOADS["mixed_12x12_n24_s12"]
+    Y = device_signals(synth, w, torch.bfloat16)
+    e1, e2 = synth.initial_dictionaries(w)
+
+    def fresh():
+        return api.Problem(Y, torch.from_numpy(e1.T.copy()).cuda(), torch.from_numpy(e2.T.copy()).cuda(), w.s)
+
+    pr, trace, dt = timed_learn(api, fresh, w.iters)
+    nsub = 5000
+    Ysub = Y[:nsub].double().cpu().numpy().transpose(0, 2, 1)  # the rounded signals, math layout
+    _, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+    r_g = pr.res2[:nsub].double().cpu().numpy()
+    return {"workload": w.name, "N": w.N, "steps": w.iters, "dtype": "bf16 signals, f32 arithmetic, f64 solves",
+            "value": w.N * w.iters / dt, "unit": "signals/s per iteration", "ms_per_step": dt / w.iters * 1e3,
+            "rmse_first": float(trace[0][0]), "rmse_final": float(trace[0][-1]),
+            "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())), "omp_kernel": kernel_name(api, w)}
+
+
+def uneven_workload(api, oracle, synth):
+    """The uneven batch: four problems of different shapes and sizes (370k signals in all)
+    learned together in one call, K = 10."""
+    import torch
+    ws = [synth.WORKLOADS[n] for n in synth.UNEVEN_BATCH]
+    Ys = [device_signals(synth, w, torch.float32) for w in ws]
+    inits = [synth.initial_dictionaries(w) for w in ws]
+
+    def fresh():
+        return [api.Problem(Y, torch.from_numpy(e1.T.copy()).cuda(), torch.from_numpy(e2.T.copy()).cuda(), w.s)
+                for Y, (e1, e2), w in zip(Ys, inits, ws)]
+
+    K = ws[0].iters
+    probs, trace, dt = timed_learn(api, fresh, K)
+    ntot = sum(w.N for w in ws)
+    per = []
+    for w, pr, tr in zip(ws, probs, trace):
+        nsub = 2000
+        Ysub = synth.signals(w, 0, nsub)
+        _, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+        r_g = pr.res2[:nsub].double().cpu().numpy()
+        per.append({"workload": w.name, "N": w.N, "rmse_final": float(tr[-1]),
+                    "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
+                    "omp_kernel": kernel_name(api, w)})
+    return {"N": ntot, "steps": K, "value": ntot * K / dt, "unit": "signals/s per iteration",
+            "ms_per_step": dt / K * 1e3, "problems": per}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +227,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-steps", type=int, default=5)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one elementwise FP32 copy of MIB MiB (reads and writes MIB MiB): "
                          "the reference dispatch that scales hardware byte counters")
@@ -238,6 +323,8 @@ def main():
     learned = None
     if not args.no_learned and dtype == torch.float32:
         learned = learned_vs_plain(args, api, oracle, synth)
+    mixed = None if args.no_mixed else mixed_workload(api, oracle, synth)
+    uneven = None if args.no_uneven else uneven_workload(api, oracle, synth)
 
     symbol = kernel_symbol(w, tuned)
     out = {
@@ -270,6 +357,8 @@ def main():
         "rmse_final": float(trace[-1]),
         "rmse_vs_oracle": rmse_ratio,
         "learned_vs_plain": learned,
+        "mixed_precision": mixed,
+        "uneven_batch": uneven,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
