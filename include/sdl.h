@@ -101,7 +101,9 @@ typedef struct sdl_options {
   int32_t use_graph;        /* sdl_learn: replay one iteration as a HIP graph (default 1) */
   int32_t check_finite;     /* scan Y and dictionaries for NaN/Inf first (default 0) */
   int32_t timing;           /* fill stats->kernel_ms (eager launches with events; default 0) */
-  int32_t kernel;           /* sparse-coding kernel: 0 auto, 1 generic, 2 register-resident fast path */
+  int32_t kernel;           /* sparse-coding kernel: 0 auto, 1 generic, 2 register-resident multi-signal
+                               (FP32), 3 register-resident one wave per signal (large shapes); auto picks
+                               2, then 3, then 1, as compiled for the shape */
   double stop_rel;          /* OMP stops when max |corr| <= stop_rel*||Y_k||_F; default 1e-14 (FP64), 1e-6 (FP32) */
   double dep_eps;           /* OMP stops when the new Gram pivot <= dep_eps*G_aa; default 1e-10 */
   double pivot_fp64;        /* FP32: pivots below pivot_fp64*G_aa are recomputed in FP64; default 1e-3 */

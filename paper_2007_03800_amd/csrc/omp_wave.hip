@@ -1,0 +1,314 @@
+// 2D-OMP for large shapes: one wave64 per signal, correlations in registers.
+//
+// Same method and Gram-form recurrences as omp_generic.hip (2D-OMP, Sec. III step 1;
+// Gram entries G1[i,i'] G2[j,j'], text after Algorithm 1), for shapes whose n1 x n2
+// correlations do not fit the multi-signal layouts of omp_fast.hip / omp_mfma.hip
+// (hundreds to ~2000 atoms, s up to 32):
+//
+//  * Lane (sr, sc) of an LR x LC grid (LR*LC <= 64) holds the correlations of atoms
+//    i = sr + LR*ri, j = sc + LC*cj in E = (n1/LR)(n2/LC) registers, so each Gram-form
+//    refresh term gamma_k G1[:, i_k] G2[j_k, :] is an E-element rank-one update from
+//    NRI + NCJ contiguous LDS reads.
+//  * The support, coefficients, Cholesky pivots and the triangular solves are spread
+//    over lanes (lane k holds element k of the support): each solve step broadcasts one
+//    value with readlane and updates the remaining lanes, so a step costs a few
+//    instructions instead of a serial loop in every lane.  The Cholesky rows sit in LDS.
+//  * Loops over the greedy step and the support are runtime loops: code size does not
+//    grow with s.  Chosen atoms are masked explicitly (one bit per register element),
+//    as in the generic kernel and the FP64 reference.
+//  * FP32 pivots below pivot_fp64 * G_aa are recomputed in FP64.
+// No TMOD sums epilogue: with this kernel the dictionary updates use the standalone
+// sums kernel.
+#include <limits.h>
+
+#include "sdl_internal.h"
+
+namespace sdl {
+namespace {
+
+constexpr int kWaveWaves = 4;  // signals (waves) per workgroup
+constexpr int kWaveMaxBlocks = 4096;
+
+template <int M1_, int M2_, int N1_, int N2_, int S_, int LR_, int LC_>
+struct WCfg {
+  static constexpr int M1 = M1_, M2 = M2_, N1 = N1_, N2 = N2_, S = S_, LR = LR_, LC = LC_;
+  static constexpr int LG = LR * LC, NRI = N1 / LR, NCJ = N2 / LC, E = NRI * NCJ;
+  static constexpr int M = M1 * M2, NL = S * (S - 1) / 2 + 1;  // strictly lower rows of L
+  static constexpr int WS = N1 * M2;                             // first-correlation staging
+  static constexpr int PW = M + WS + NL + 1;                     // per-wave LDS words (+1: odd stride)
+  static_assert(N1 % LR == 0 && N2 % LC == 0 && LG <= 64, "lane grid must tile the atoms");
+  static_assert(E <= 64, "one mask bit per register element");
+  static_assert(S <= LG, "support element k lives in lane k of the grid");
+};
+
+constexpr int tril(int k, int l) { return k * (k - 1) / 2 + l; }  // L[k][l], l < k
+
+template <typename U>
+__device__ inline U bcast(U v, int k) {  // value of lane k (k uniform)
+  if constexpr (sizeof(U) == 4) {
+    return __builtin_bit_cast(U, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __builtin_bit_cast(U, ((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+
+template <typename U>
+__device__ inline U wave_sum(U v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward solve L w = b for the new Cholesky row, in precision U, with the support
+// spread over lanes: lane k < t holds b_k (= G_{k,a}) and dinv_k; returns w_k in lane k
+// and |w|^2 in every lane.  Lrow: packed strictly-lower rows of L (tril).
+template <typename U, typename T>
+__device__ inline U forward_row(U b, U dinv, const T* Lrow, int t, int lane, U& ww) {
+  U w = 0;
+  ww = 0;
+  for (int k = 0; k < t; ++k) {
+    const U wk = bcast(b, k) * bcast(dinv, k);
+    ww += wk * wk;
+    if (lane == k) w = wk;
+    if (lane > k && lane < t) b -= (U)Lrow[tril(lane, k)] * wk;
+  }
+  return w;
+}
+
+template <typename T, class C>
+__global__ void __launch_bounds__(kWave* kWaveWaves) omp_wave_kernel(OmpArgs<T> a) {
+  constexpr int M1 = C::M1, M2 = C::M2, N1 = C::N1, N2 = C::N2, S = C::S, LR = C::LR;
+  constexpr int NRI = C::NRI, NCJ = C::NCJ, E = C::E, M = C::M;
+  __shared__ T sD1[M1 * N1];                  // D1[p, i] at p + M1 i
+  __shared__ T sD2[M2 * N2];                  // D2[q, j] at q + M2 j
+  __shared__ __align__(16) T sG1P[N1 * N1];   // [ik][sr][ri] = G1[sr + LR ri, ik]
+  __shared__ __align__(16) T sG2P[N2 * N2];   // [jk][sc][cj] = G2[jk, sc + LC cj]
+  __shared__ T sW[kWaveWaves][C::PW];
+
+  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
+  for (int e = tid; e < M1 * N1; e += blockDim.x) sD1[e] = a.D1[e];
+  for (int e = tid; e < M2 * N2; e += blockDim.x) sD2[e] = a.D2[e];
+  for (int e = tid; e < N1 * N1; e += blockDim.x) {
+    const int ik = e / N1, rem = e % N1, r = rem / NRI, ri = rem % NRI;
+    sG1P[e] = a.G1[(r + LR * ri) + N1 * ik];
+  }
+  for (int e = tid; e < N2 * N2; e += blockDim.x) {
+    const int jk = e / N2, rem = e % N2, c = rem / NCJ, cj = rem % NCJ;
+    sG2P[e] = a.G2[jk + N2 * (c + C::LC * cj)];
+  }
+  __syncthreads();
+
+  const bool act = lane < C::LG;
+  const int sr = lane % LR, sc = (lane / LR) % C::LC;
+  T* ys = sW[wv];
+  T* Ws = ys + M;
+  T* Lrow = Ws + C::WS;
+  // G1[i, i'] and G2[j, j'] from the permuted tables (both are symmetric)
+  auto g1 = [&](int i, int ik) { return sG1P[ik * N1 + (i % LR) * NRI + i / LR]; };
+  auto g2 = [&](int jk, int j) { return sG2P[jk * N2 + (j % C::LC) * NCJ + j / C::LC]; };
+
+  for (int64_t k = (int64_t)blockIdx.x * kWaveWaves + wv; k < a.N; k += (int64_t)gridDim.x * kWaveWaves) {
+    T yy = 0;
+    for (int e = lane; e < M; e += kWave) {
+      const T v = a.Yh ? (T)bf16_to_float(a.Yh[k * M + e]) : a.Y[k * M + e];
+      ys[e] = v;
+      yy += v * v;
+    }
+    const T ynorm = sqrt(wave_sum(yy));
+    wave_sync();
+    // C = (D1^T Y) D2: W = D1^T Y staged in LDS, then each lane's block of C
+    for (int e = lane; e < C::WS; e += kWave) {
+      const int i = e % N1, q = e / N1;
+      T v = 0;
+      for (int p = 0; p < M1; ++p) v += sD1[p + M1 * i] * ys[p + M1 * q];
+      Ws[e] = v;
+    }
+    wave_sync();
+    T corr[E];
+#pragma unroll
+    for (int ri = 0; ri < NRI; ++ri)
+#pragma unroll
+      for (int cj = 0; cj < NCJ; ++cj) {
+        T v = 0;
+        if (act) {
+          const int i = sr + LR * ri, j = sc + C::LC * cj;
+          for (int q = 0; q < M2; ++q) v += Ws[i + N1 * q] * sD2[q + M2 * j];
+        }
+        corr[ri * NCJ + cj] = v;
+      }
+    unsigned long long used = 0ull;  // bit e: register element e is a chosen atom
+    // support element k lives in lane k
+    T my_x = 0, my_dinv = 0;
+    int my_i = 0, my_j = 0;
+    int t = 0;
+    bool early = false;
+    const T stop_thr = (T)a.stop_rel * ynorm;
+    for (; t < S; ++t) {
+      // largest |corr| over the unselected atoms; ties to the smaller atom index
+      T bv = T(-1), bs = 0;
+      int ba = INT_MAX;
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int ri = e / NCJ, cj = e % NCJ;
+          const int at = (sr + LR * ri) + N1 * (sc + C::LC * cj);
+          const T v = fabs(corr[e]);
+          const bool take = !((used >> e) & 1ull) && (v > bv || (v == bv && at < ba));
+          bv = take ? v : bv;
+          bs = take ? corr[e] : bs;
+          ba = take ? at : ba;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const T ov = __shfl_xor(bv, o, kWave), os = __shfl_xor(bs, o, kWave);
+        const int oa = __shfl_xor(ba, o, kWave);
+        const bool take = ov > bv || (ov == bv && oa < ba);
+        bv = take ? ov : bv;
+        bs = take ? os : bs;
+        ba = take ? oa : ba;
+      }
+      if (ba == INT_MAX || !(bv > stop_thr)) {
+        early = true;
+        break;
+      }
+      const int ia = ba % N1, ja = ba / N1;
+      const T gaa = g1(ia, ia) * g2(ja, ja);
+      const T bk = lane < t ? g1(my_i, ia) * g2(ja, my_j) : T(0);
+      T ww;
+      T w = forward_row<T, T>(bk, my_dinv, Lrow, t, lane, ww);
+      T d2 = gaa - ww;
+      if (sizeof(T) == 4 && d2 < (T)a.pivot_fp64 * gaa) {
+        // small pivot: the row again in FP64 (cancellation in G_aa - |w|^2)
+        const double bk64 = lane < t ? (double)g1(my_i, ia) * (double)g2(ja, my_j) : 0.0;
+        double ww64;
+        const double w64 = forward_row<double, T>(bk64, (double)my_dinv, Lrow, t, lane, ww64);
+        w = (T)w64;
+        d2 = (T)((double)gaa - ww64);
+        if (lane == 0) atomicAdd(&a.counters[kCtrFp64Pivot], 1ull);
+      }
+      if (!(d2 > (T)a.dep_eps * gaa)) {
+        early = true;
+        break;
+      }
+      // v = L^{-T} w, from the last support element up
+      T c = w, v = 0;
+      for (int q = t - 1; q >= 0; --q) {
+        const T vq = bcast(c, q) * bcast(my_dinv, q);
+        if (lane == q) v = vq;
+        if (lane < q) c -= (T)Lrow[tril(q, lane)] * vq;
+      }
+      const T cst = bs / d2;
+      if (lane < t) {
+        Lrow[tril(t, lane)] = w;
+        my_x -= cst * v;
+      }
+      if (lane == t) {
+        my_x = cst;
+        my_i = ia;
+        my_j = ja;
+        my_dinv = (T)1 / sqrt(d2);
+      }
+      if (act && sr == ia % LR && sc == ja % C::LC) used |= 1ull << ((ia / LR) * NCJ + ja / C::LC);
+      wave_sync();
+      if (t + 1 < S) {
+        // corr <- corr - cst (G_{:,a} - G_{:,S} v): terms gamma_q G1[:, i_q] G2[j_q, :]
+        for (int q = 0; q <= t; ++q) {
+          const T gq = q == t ? -cst : cst * bcast(v, q);
+          const int iq = q == t ? ia : bcast(my_i, q), jq = q == t ? ja : bcast(my_j, q);
+          if (!act) continue;
+          const T* p1 = sG1P + iq * N1 + sr * NRI;
+          const T* p2 = sG2P + jq * N2 + sc * NCJ;
+          T u1[NRI];
+#pragma unroll
+          for (int ri = 0; ri < NRI; ++ri) u1[ri] = gq * p1[ri];
+#pragma unroll
+          for (int cj = 0; cj < NCJ; ++cj) {
+            const T u2 = p2[cj];
+#pragma unroll
+            for (int ri = 0; ri < NRI; ++ri) corr[ri * NCJ + cj] += u1[ri] * u2;
+          }
+        }
+      }
+    }
+    // explicit residual Y - sum_q x_q d1_{i_q} d2_{j_q}^T
+    T rr = 0;
+    for (int e = lane; e < M; e += kWave) {
+      const int p = e % M1, q = e / M1;
+      T r = ys[e];
+      for (int u = 0; u < t; ++u) r -= bcast(my_x, u) * sD1[p + M1 * bcast(my_i, u)] * sD2[q + M2 * bcast(my_j, u)];
+      rr += r * r;
+    }
+    rr = wave_sum(rr);
+    if (lane < S) {
+      a.supp[k * S + lane] = lane < t ? my_i + N1 * my_j : -1;
+      a.coef[k * S + lane] = lane < t ? my_x : T(0);
+    }
+    if (lane == 0) {
+      if (a.res2) a.res2[k] = rr;
+      if (early) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+    }
+    wave_sync();
+  }
+}
+
+template <typename T, class C>
+hipError_t launch_wcfg(const OmpArgs<T>& a, hipStream_t st) {
+  int64_t blocks = (a.N + kWaveWaves - 1) / kWaveWaves;
+  if (blocks > kWaveMaxBlocks) blocks = kWaveMaxBlocks;
+  hipLaunchKernelGGL((omp_wave_kernel<T, C>), dim3((unsigned)blocks), dim3(kWave * kWaveWaves), 0, st, a);
+  return hipGetLastError();
+}
+
+struct WaveVariant {
+  int m1, m2, n1, n2, s;
+  hipError_t (*f32)(const OmpArgs<float>&, hipStream_t);
+  hipError_t (*f64)(const OmpArgs<double>&, hipStream_t);
+};
+
+// Shapes with a one-wave-per-signal register kernel: (m1, m2, n1, n2, s, lane grid LR x LC)
+#define SDL_WAVE_SHAPES(X)                                                                      \
+  X(12, 12, 20, 20, 10, 4, 10) X(12, 12, 24, 24, 12, 8, 8) X(16, 16, 32, 32, 16, 8, 8)           \
+  X(32, 24, 48, 36, 20, 16, 4)
+
+const WaveVariant kWaveVariants[] = {
+#define X(A_, B_, C_, D_, E_, F_, G_) \
+  {A_, B_, C_, D_, E_, &launch_wcfg<float, WCfg<A_, B_, C_, D_, E_, F_, G_>>, &launch_wcfg<double, WCfg<A_, B_, C_, D_, E_, F_, G_>>},
+    SDL_WAVE_SHAPES(X)
+#undef X
+};
+
+const WaveVariant* find_wave(int m1, int m2, int n1, int n2, int s) {
+  for (const WaveVariant& v : kWaveVariants)
+    if (v.m1 == m1 && v.m2 == m2 && v.n1 == n1 && v.n2 == n2 && v.s == s) return &v;
+  return nullptr;
+}
+
+}  // namespace
+
+bool omp_wave_supported(int m1, int m2, int n1, int n2, int s) { return find_wave(m1, m2, n1, n2, s) != nullptr; }
+
+template <typename T>
+hipError_t launch_omp_wave(const OmpArgs<T>& a, hipStream_t st) {
+  const WaveVariant* v = find_wave(a.m1, a.m2, a.n1, a.n2, a.s);
+  if (!v || a.index || a.sums_side) return hipErrorInvalidValue;
+  if (a.N == 0) return hipSuccess;
+  if constexpr (sizeof(T) == 4)
+    return v->f32(a, st);
+  else
+    return v->f64(a, st);
+}
+
+template hipError_t launch_omp_wave<float>(const OmpArgs<float>&, hipStream_t);
+template hipError_t launch_omp_wave<double>(const OmpArgs<double>&, hipStream_t);
+
+}  // namespace sdl

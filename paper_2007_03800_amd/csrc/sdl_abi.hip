@@ -157,7 +157,7 @@ int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_
   if (o.prec != SDL_FP64 && o.prec != SDL_FP32 && o.prec != SDL_BF16)
     return fail(SDL_E_INVAL, "prec = %d is not an sdl_prec", o.prec);
   if (o.schedule != 0 && o.schedule != 1) return fail(SDL_E_INVAL, "schedule = %d (0 or 1)", o.schedule);
-  if (o.kernel < 0 || o.kernel > 2) return fail(SDL_E_INVAL, "kernel = %d (0, 1 or 2)", o.kernel);
+  if (o.kernel < 0 || o.kernel > 3) return fail(SDL_E_INVAL, "kernel = %d (0..3)", o.kernel);
   const size_t elem = o.prec == SDL_FP64 ? 8 : 4;
   for (int q = 0; q < nprob; ++q) {
     const sdl_problem& r = p[q];
@@ -306,7 +306,7 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
 
 template <typename T>
 bool use_fast(const sdl_problem& r, const Opt& o) {
-  return o.kernel != 1 && omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s);
+  return (o.kernel == 0 || o.kernel == 2) && omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s);
 }
 
 // sums_side != 0 (register-resident path only): the sweep also writes the partial
@@ -320,8 +320,13 @@ int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, i
   if (o.kernel == 2 && !fast)
     return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for m=%dx%d n=%dx%d s=%d in this precision", r.m1,
                 r.m2, r.n1, r.n2, r.s);
+  const bool wave = !fast && sums_side == 0 && (o.kernel == 0 || o.kernel == 3) &&
+                    omp_wave_supported(r.m1, r.m2, r.n1, r.n2, r.s);
+  if (o.kernel == 3 && !wave)
+    return fail(SDL_E_UNSUPPORTED, "no one-wave-per-signal kernel for m=%dx%d n=%dx%d s=%d", r.m1, r.m2, r.n1, r.n2,
+                r.s);
   SDL_TRY(L.begin(0));
-  HIP_TRY(fast ? launch_omp_fast<T>(a, L.st) : launch_omp_generic<T>(a, L.st));
+  HIP_TRY(fast ? launch_omp_fast<T>(a, L.st) : wave ? launch_omp_wave<T>(a, L.st) : launch_omp_generic<T>(a, L.st));
   return L.end();
 }
 

@@ -78,6 +78,11 @@ template <typename T>
 bool omp_fast_supported(int m1, int m2, int n1, int n2, int s);
 template <typename T>
 hipError_t launch_omp_fast(const OmpArgs<T>& a, hipStream_t st);
+// One wave per signal with the correlations in registers (omp_wave.hip), for the large
+// shapes it is compiled for; FP32 and FP64; no index mode, no sums epilogue.
+bool omp_wave_supported(int m1, int m2, int n1, int n2, int s);
+template <typename T>
+hipError_t launch_omp_wave(const OmpArgs<T>& a, hipStream_t st);
 // Matrix-core variants (omp_mfma.hip): four lanes per signal, refresh on 4x4x1 MFMA.
 struct MfmaVariant {
   int m1, m2, n1, n2, s, wpe;
