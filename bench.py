@@ -162,7 +162,9 @@ def timed_learn(api, fresh, K):
 def kernel_name(api, w):
     t = api.tuned_config(w.m1, w.m2, w.n1, w.n2, w.s)
     if t is None:
-        return "generic (one wave per signal)"
+        return "generic (one wave per signal, all in LDS)"
+    if t[3] == 2:
+        return "register-resident, one wave per signal, lanes %dx%d" % (t[0], t[1])
     return "register-resident lanes %dx%d, %d waves/SIMD%s" % (t[0], t[1], t[2], ", refresh on MFMA" if t[3] else "")
 
 

@@ -153,15 +153,18 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
 
 /* Kernel configuration currently used for an FP32 shape: lanes per signal split
  * over atom rows (lanes_row) and columns (lanes_col), register budget in waves
- * per SIMD, whether the correlation refresh runs on the matrix cores, and the tuned
- * time in ms (0 if not tuned).  Returns 0 if the shape has a register-resident
- * kernel, SDL_E_UNSUPPORTED if it runs on the generic kernel. */
+ * per SIMD, the kind in matrix_core (0: multi-signal on the vector ALUs, 1: correlation
+ * refresh on the matrix cores, 2: one wave per signal, whose dictionary sums run in
+ * the standalone sums kernel), and the tuned time in ms (0 if not tuned; for kind 2
+ * it includes the D1-side sums).  Returns 0 if the shape has a register-resident
+ * kernel, SDL_E_UNSUPPORTED if it runs on the generic kernel.  The autotuner also times
+ * kind 2 where it exists and keeps it if it beats the best fused variant. */
 int sdl_tuned_config(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* lanes_row,
                      int32_t* lanes_col, int32_t* waves_per_simd, int32_t* matrix_core, double* ms);
 
 /* Register-resident kernel variants compiled for an FP32 shape: writes up to `cap`
- * quadruples (lanes_row, lanes_col, waves_per_simd, matrix_core) to out (host,
- * 4*cap int32) and returns how many exist (0: the shape runs on the generic kernel). */
+ * quadruples (lanes_row, lanes_col, waves_per_simd, kind as in sdl_tuned_config) to out
+ * (host, 4*cap int32) and returns how many exist (0: the shape runs on the generic kernel). */
 int sdl_kernel_variants(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t* out, int32_t cap);
 
 /* Force the variant used for an FP32 shape for the rest of the process (instead of

@@ -30,6 +30,7 @@ struct Choice {
 
 std::mutex g_tune_mu;
 std::map<Key, Choice> g_choice;
+std::map<Key, Choice> g_wave;  // shapes for which the one-wave-per-signal path won (id unused)
 bool g_cache_loaded = false;
 
 int find_variant(int m1, int m2, int n1, int n2, int s, int lr, int lc, int wpe, int mfma) {
@@ -53,8 +54,15 @@ void load_cache_locked() {
   int m1, m2, n1, n2, s, lr, lc, wpe, mf;
   double ms;
   while (fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &m1, &m2, &n1, &n2, &s, &lr, &lc, &wpe, &mf, &ms) == 10) {
+    if (mf == 2) {  // one-wave-per-signal path
+      g_wave[Key(m1, m2, n1, n2, s)] = Choice{0, ms};
+      continue;
+    }
     const int id = find_variant(m1, m2, n1, n2, s, lr, lc, wpe, mf);
-    if (id >= 0) g_choice[Key(m1, m2, n1, n2, s)] = Choice{id, ms};
+    if (id >= 0) {
+      g_choice[Key(m1, m2, n1, n2, s)] = Choice{id, ms};
+      g_wave.erase(Key(m1, m2, n1, n2, s));
+    }
   }
   fclose(f);
 }
@@ -86,6 +94,40 @@ int omp_fast_choice(int m1, int m2, int n1, int n2, int s) {
 void omp_fast_set_choice(int m1, int m2, int n1, int n2, int s, int id) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_choice[Key(m1, m2, n1, n2, s)] = Choice{id, 0.0};
+}
+
+bool wave_chosen(int m1, int m2, int n1, int n2, int s) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_cache_locked();
+  return g_wave.count(Key(m1, m2, n1, n2, s)) > 0;
+}
+
+double wave_choice_ms(int m1, int m2, int n1, int n2, int s) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_wave.find(Key(m1, m2, n1, n2, s));
+  return it == g_wave.end() ? 0.0 : it->second.ms;
+}
+
+void set_wave_choice(int m1, int m2, int n1, int n2, int s, bool on, double ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_cache_locked();
+  const Key k(m1, m2, n1, n2, s);
+  if (!on) {
+    g_wave.erase(k);
+    return;
+  }
+  g_wave[k] = Choice{0, ms};
+  int lr = 0, lc = 0;
+  if (ms > 0.0 && omp_wave_grid(m1, m2, n1, n2, s, &lr, &lc)) {
+    const char* path = getenv("SDL_TUNE_CACHE");
+    if (path && *path) {
+      FILE* f = fopen(path, "a");
+      if (f) {
+        fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f\n", m1, m2, n1, n2, s, lr, lc, 0, 2, ms);
+        fclose(f);
+      }
+    }
+  }
 }
 
 // Times every variant of one problem's shape; returns hipSuccess and the chosen id/ms.

@@ -270,7 +270,7 @@ hipError_t launch_wcfg(const OmpArgs<T>& a, hipStream_t st) {
 }
 
 struct WaveVariant {
-  int m1, m2, n1, n2, s;
+  int m1, m2, n1, n2, s, lr, lc;
   hipError_t (*f32)(const OmpArgs<float>&, hipStream_t);
   hipError_t (*f64)(const OmpArgs<double>&, hipStream_t);
 };
@@ -282,7 +282,7 @@ struct WaveVariant {
 
 const WaveVariant kWaveVariants[] = {
 #define X(A_, B_, C_, D_, E_, F_, G_) \
-  {A_, B_, C_, D_, E_, &launch_wcfg<float, WCfg<A_, B_, C_, D_, E_, F_, G_>>, &launch_wcfg<double, WCfg<A_, B_, C_, D_, E_, F_, G_>>},
+  {A_, B_, C_, D_, E_, F_, G_, &launch_wcfg<float, WCfg<A_, B_, C_, D_, E_, F_, G_>>, &launch_wcfg<double, WCfg<A_, B_, C_, D_, E_, F_, G_>>},
     SDL_WAVE_SHAPES(X)
 #undef X
 };
@@ -296,6 +296,14 @@ const WaveVariant* find_wave(int m1, int m2, int n1, int n2, int s) {
 }  // namespace
 
 bool omp_wave_supported(int m1, int m2, int n1, int n2, int s) { return find_wave(m1, m2, n1, n2, s) != nullptr; }
+
+bool omp_wave_grid(int m1, int m2, int n1, int n2, int s, int* lr, int* lc) {
+  const WaveVariant* v = find_wave(m1, m2, n1, n2, s);
+  if (!v) return false;
+  *lr = v->lr;
+  *lc = v->lc;
+  return true;
+}
 
 template <typename T>
 hipError_t launch_omp_wave(const OmpArgs<T>& a, hipStream_t st) {

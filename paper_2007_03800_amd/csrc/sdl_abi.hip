@@ -306,7 +306,8 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
 
 template <typename T>
 bool use_fast(const sdl_problem& r, const Opt& o) {
-  return (o.kernel == 0 || o.kernel == 2) && omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s);
+  if (!omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s)) return false;
+  return o.kernel == 2 || (o.kernel == 0 && !wave_chosen(r.m1, r.m2, r.n1, r.n2, r.s));
 }
 
 // sums_side != 0 (register-resident path only): the sweep also writes the partial
@@ -367,9 +368,8 @@ int run_reduce_solve(int side, const sdl_problem& r, const PBuf& b, const Plan& 
   return L.end();
 }
 
-// one TMOD half-step from the codes in supp/coef: standalone sums -> reduce -> solve (+ rescale)
 template <typename T>
-int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bool rescale, Launcher& L) {
+TmodArgs<T> tmod_args(int side, const sdl_problem& r, const PBuf& b, const Plan& pl) {
   TmodArgs<T> a;
   a.side = side;
   a.m1 = r.m1; a.m2 = r.m2; a.n1 = r.n1; a.n2 = r.n2; a.s = r.s; a.N = r.N;
@@ -378,6 +378,13 @@ int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bo
   a.Dother = (const T*)(side == 1 ? b.Dc2 : b.Dc1);
   a.supp = r.supp;
   a.coef = (const T*)r.coef;
+  return a;
+}
+
+// one TMOD half-step from the codes in supp/coef: standalone sums -> reduce -> solve (+ rescale)
+template <typename T>
+int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bool rescale, Launcher& L) {
+  const TmodArgs<T> a = tmod_args<T>(side, r, b, pl);
   const int nblk = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2) : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1);
   SDL_TRY(L.begin(1));
   HIP_TRY(launch_tmod_sums<T>(a, b.part, L.st));
@@ -673,6 +680,34 @@ namespace sdl {
 int abi_fail(int st, const char* msg) { return fail(st, "%s", msg); }
 }  // namespace sdl
 
+namespace {
+
+// Median over reps of the device time of f() (one warm-up call first), with events on st.
+template <class F>
+int time_median(hipStream_t st, int reps, double* out, F f) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(f());
+  std::vector<float> t;
+  for (int r = 0; r < reps; ++r) {
+    HIP_TRY(hipEventRecord(e0, st));
+    HIP_TRY(f());
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    t.push_back(ms);
+  }
+  HIP_TRY(hipEventDestroy(e0));
+  HIP_TRY(hipEventDestroy(e1));
+  std::sort(t.begin(), t.end());
+  *out = t[t.size() / 2];
+  return SDL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void sdl_default_options(sdl_options* o) {
@@ -748,6 +783,17 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
     int id;
     double ms;
     HIP_TRY(autotune_problem(a, st, reps, &id, &ms));
+    if (id >= 0 && omp_wave_supported(p[q].m1, p[q].m2, p[q].n1, p[q].n2, p[q].s)) {
+      // the alternative path: one wave per signal, then the standalone D1-side sums
+      OmpArgs<float> aw = omp_args<float>(p[q], pl.pb[q], opt, pl);
+      const TmodArgs<float> ta = tmod_args<float>(1, p[q], pl.pb[q], pl);
+      double wms = 0.0;
+      SDL_TRY(time_median(st, reps, &wms, [&]() -> hipError_t {
+        hipError_t e = launch_omp_wave<float>(aw, st);
+        return e != hipSuccess ? e : launch_tmod_sums<float>(ta, pl.pb[q].part, st);
+      }));
+      set_wave_choice(p[q].m1, p[q].m2, p[q].n1, p[q].n2, p[q].s, wms < ms, wms);
+    }
   }
   HIP_TRY(hipStreamSynchronize(st));
   return SDL_OK;
@@ -774,8 +820,13 @@ int sdl_tuned_config(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, 
                      int32_t* lanes_col, int32_t* waves_per_simd, int32_t* matrix_core, double* ms) {
   int lr = 0, lc = 0, wpe = 0, mf = 0;
   double t = 0.0;
-  if (!tuned_config(m1, m2, n1, n2, s, &lr, &lc, &wpe, &mf, &t))
+  const bool fast = omp_fast_supported<float>(m1, m2, n1, n2, s);
+  if ((!fast || wave_chosen(m1, m2, n1, n2, s)) && omp_wave_grid(m1, m2, n1, n2, s, &lr, &lc)) {
+    mf = 2;  // one wave per signal
+    t = wave_choice_ms(m1, m2, n1, n2, s);
+  } else if (!tuned_config(m1, m2, n1, n2, s, &lr, &lc, &wpe, &mf, &t)) {
     return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for this shape");
+  }
   if (lanes_row) *lanes_row = lr;
   if (lanes_col) *lanes_col = lc;
   if (waves_per_simd) *waves_per_simd = wpe;
@@ -789,7 +840,15 @@ int sdl_kernel_variants(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t 
   const int n = omp_fast_variants(m1, m2, n1, n2, s, ids, 64);
   for (int i = 0; i < n && i < cap && i < 64 && out; ++i)
     omp_fast_variant_info(ids[i], &out[4 * i], &out[4 * i + 1], &out[4 * i + 2], &out[4 * i + 3]);
-  return n;
+  int lr, lc;
+  if (!omp_wave_grid(m1, m2, n1, n2, s, &lr, &lc)) return n;
+  if (out && n < cap) {
+    out[4 * n] = lr;
+    out[4 * n + 1] = lc;
+    out[4 * n + 2] = 0;
+    out[4 * n + 3] = 2;
+  }
+  return n + 1;
 }
 
 int sdl_set_kernel_variant(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, int32_t lanes_row,
@@ -801,8 +860,14 @@ int sdl_set_kernel_variant(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32
     omp_fast_variant_info(ids[i], &lr, &lc, &wpe, &mf);
     if (lr == lanes_row && lc == lanes_col && wpe == waves_per_simd && mf == matrix_core) {
       omp_fast_set_choice(m1, m2, n1, n2, s, ids[i]);
+      set_wave_choice(m1, m2, n1, n2, s, false, 0.0);
       return SDL_OK;
     }
+  }
+  int lr, lc;
+  if (matrix_core == 2 && omp_wave_grid(m1, m2, n1, n2, s, &lr, &lc) && lr == lanes_row && lc == lanes_col) {
+    set_wave_choice(m1, m2, n1, n2, s, true, 0.0);
+    return SDL_OK;
   }
   return fail(SDL_E_UNSUPPORTED, "no kernel variant (%d, %d, %d) for this shape", lanes_row, lanes_col,
               waves_per_simd);

@@ -81,6 +81,12 @@ hipError_t launch_omp_fast(const OmpArgs<T>& a, hipStream_t st);
 // One wave per signal with the correlations in registers (omp_wave.hip), for the large
 // shapes it is compiled for; FP32 and FP64; no index mode, no sums epilogue.
 bool omp_wave_supported(int m1, int m2, int n1, int n2, int s);
+bool omp_wave_grid(int m1, int m2, int n1, int n2, int s, int* lanes_row, int* lanes_col);
+// Per-shape choice between the fused multi-signal path and the one-wave-per-signal
+// path (sparse coding + standalone sums), made by the autotuner or forced (autotune.hip).
+bool wave_chosen(int m1, int m2, int n1, int n2, int s);
+void set_wave_choice(int m1, int m2, int n1, int n2, int s, bool on, double ms);
+double wave_choice_ms(int m1, int m2, int n1, int n2, int s);
 template <typename T>
 hipError_t launch_omp_wave(const OmpArgs<T>& a, hipStream_t st);
 // Matrix-core variants (omp_mfma.hip): four lanes per signal, refresh on 4x4x1 MFMA.

@@ -32,7 +32,7 @@ def test_variant_parity(shape, variant, rng):
     so, co, ro = oracle.omp(Y, d1, d2, s)
     api.set_kernel_variant(m1, m2, n1, n2, s, variant)
     pr = api.Problem.from_math(Y, d1, d2, s, dtype=torch.float32)
-    api.sparse_code(pr, kernel=2)
+    api.sparse_code(pr, kernel=3 if variant[3] == 2 else 2)  # kind 2: one wave per signal
     torch.cuda.synchronize()
     sg, cg, rg = pr.supp.cpu().numpy(), pr.coef.cpu().double().numpy(), pr.res2.cpu().double().numpy()
     agree, ties, bad, err = compare_codes(Y, d1, d2, sg, cg, so, co, 1e-4, 1e-4)
@@ -43,12 +43,21 @@ def test_variant_parity(shape, variant, rng):
     np.testing.assert_allclose(rg[ok], ro[ok], rtol=2e-3, atol=1e-6)
 
 
-def test_autotune_picks_a_variant(rng):
-    m1, m2, n1, n2, s = 8, 8, 16, 16, 8
+@pytest.mark.parametrize("shape", [(8, 8, 16, 16, 8), (16, 16, 32, 32, 16)], ids=lambda x: "x".join(map(str, x)))
+def test_autotune_picks_a_variant(shape, rng):
+    m1, m2, n1, n2, s = shape
     d1, d2 = rand_dicts(rng, m1, m2, n1, n2)
     Y, _ = planted(rng, 20000, d1, d2, s, noise=0.03)
     pr = api.Problem.from_math(Y, d1, d2, s, dtype=torch.float32)
     api.autotune(pr, reps=3)
     cfg = api.tuned_config(m1, m2, n1, n2, s)
+    print(shape, "tuned", cfg)
     assert cfg is not None and cfg[:4] in api.kernel_variants(m1, m2, n1, n2, s) and cfg[4] > 0
     assert api.tuned_config(5, 5, 7, 7, 3) is None
+    # whichever path won, learning with it follows the oracle
+    e1, e2 = rand_dicts(rng, m1, m2, n1, n2)
+    sub = Y[:2000]
+    ref = oracle.learn(sub, e1, e2, s, 2, p=8)
+    pr = api.Problem.from_math(sub, e1, e2, s, dtype=torch.float32)
+    tr = api.learn(pr, 2)[0]
+    np.testing.assert_allclose(tr, ref["rmse"], rtol=0.01)
