@@ -197,7 +197,10 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
 #pragma unroll
     for (int t = 0; t < S; ++t) {
       // packed keys: |corr| bits with the low 6 bits = 63 - position (position = (bj, bi, v))
-      unsigned best = 0u;
+      // independent max chains (one per tile row bi), merged at the end: short dependency depth
+      unsigned bacc[TI];
+#pragma unroll
+      for (int bi = 0; bi < TI; ++bi) bacc[bi] = 0u;
 #pragma unroll
       for (int bj = 0; bj < TJ; ++bj)
 #pragma unroll
@@ -210,8 +213,12 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
             const float c0 = al[bi * TJ + bj][v], c1 = al[bi * TJ + bj][v + 1];
             const unsigned k0v = (__float_as_uint(c0) & 0x7FFFFFC0u) | (unsigned)(63 - (e0 & 63));
             const unsigned k1v = (__float_as_uint(c1) & 0x7FFFFFC0u) | (unsigned)(63 - ((e0 + 1) & 63));
-            best = umax3(best, k0v, k1v);
+            bacc[bi] = umax3(bacc[bi], k0v, k1v);
           }
+      unsigned best = bacc[0];
+#pragma unroll
+      for (int bi = 1; bi + 1 < TI; bi += 2) best = umax3(best, bacc[bi], bacc[bi + 1]);
+      if (TI % 2 == 0) best = max(best, bacc[TI - 1]);
       // cross-lane: larger key, ties -> smaller lane (c) ; pack lane into a second word
       unsigned bkey = best;
       int blane = c;
