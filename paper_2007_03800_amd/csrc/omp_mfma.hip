@@ -45,7 +45,9 @@ struct MCfg {
   static constexpr int YS = M + 1, LD1 = M1 + 1, LD2 = M2 + 1, NLP = NL + 1;
   static constexpr int NAX = N1 > N2 ? N1 : N2, MRX = M1 > M2 ? M1 : M2;
   static constexpr int TPX = (NAX + 15) / 16, TRX = (MRX + 15) / 16, NPX = 16 * TPX + 1;
-  static constexpr int SUB = 8;  // signals per epilogue pass
+  // signals per epilogue pass: all 16 at the occupancy of 2 waves per SIMD (LDS is not the
+  // limit there), half of them at higher occupancies
+  static constexpr int SUB = WPE <= 2 ? kSigs : kSigs / 2;
   static constexpr int WORK = kSigs * NLP > SUB * MRX * NPX ? kSigs * NLP : SUB * MRX * NPX;
   static constexpr int NTILE = TPX * TPX + TRX * TPX;
   static constexpr int NENTX = NAX * NAX + MRX * NAX + 1;
@@ -75,6 +77,96 @@ __device__ inline float quad_sum(float v) {
 constexpr int tri(int k, int l) { return k * (k + 1) / 2 + l; }
 
 __device__ inline unsigned umax3(unsigned a, unsigned b, unsigned c) { return max(max(a, b), c); }
+
+// Epilogue of one group: the group's contribution to the next dictionary update's sums
+// (Corollary 1 for SIDE 1, Proposition 1 for SIDE 2), accumulated on the matrix cores.
+// Each signal's T = X D2^T (SIDE 1) or Z^T = (D1 X)^T (SIDE 2) is written column by
+// column into LDS (tc); support elements that share a row are merged in registers in
+// selection order first, so the columns are plain stores with the same sums as
+// accumulating them one element at a time.  Then P += T T^T and R^T += Yt T^T with
+// 16x16x4 MFMA over (signal, column) pairs; acc (LDS) carries the accumulators between
+// groups.
+template <class C, int SIDE>
+__device__ inline void sums_epilogue(f32x4* acc, float* tc, const float* ys, const float* Do, const float (&x)[C::S],
+                                     const int (&ia)[C::S], const int (&ja)[C::S], int g, int c, int lane) {
+  constexpr int M1 = C::M1, S = C::S, TPX = C::TPX, TRX = C::TRX, NPX = C::NPX;
+  constexpr int EMC = SIDE == 2 ? C::M1 : C::M2;  // columns of T per signal
+  constexpr int EMR = SIDE == 2 ? C::M2 : C::M1;  // rows of the right-hand side
+  constexpr int ELD = SIDE == 2 ? C::LD1 : C::LD2;
+  static_assert(EMC % kLanes == 0, "columns split over the signal's lanes");
+  const int r16 = lane % 16, kq = lane / 16;
+  // owner[t]: first support element with the same row atom as element t
+  int ra[S], owner[S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    ra[t] = SIDE == 1 ? ia[t] : ja[t];
+    owner[t] = t;
+#pragma unroll
+    for (int u = t - 1; u >= 0; --u) owner[t] = (ra[u] == ra[t]) ? u : owner[t];
+  }
+  f32x4 accP[TPX][TPX], accR[TRX][TPX];
+#pragma unroll
+  for (int i = 0; i < TPX; ++i)
+#pragma unroll
+    for (int j = 0; j < TPX; ++j) accP[i][j] = acc[(i * TPX + j) * kWave];
+#pragma unroll
+  for (int i = 0; i < TRX; ++i)
+#pragma unroll
+    for (int j = 0; j < TPX; ++j) accR[i][j] = acc[(TPX * TPX + i * TPX + j) * kWave];
+#pragma unroll
+  for (int pass = 0; pass < kSigs; pass += C::SUB) {
+    if (g >= pass && g < pass + C::SUB) {
+#pragma unroll
+      for (int u2 = 0; u2 < EMC / kLanes; ++u2) {
+        const int cc = c + kLanes * u2;
+        float v[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) v[t] = x[t] * Do[cc + ELD * (SIDE == 1 ? ja[t] : ia[t])];
+#pragma unroll
+        for (int t = 1; t < S; ++t)
+#pragma unroll
+          for (int u = 0; u < t; ++u) v[u] = owner[t] == u ? v[u] + v[t] : v[u];
+        float* col = tc + ((g - pass) * EMC + cc) * NPX;
+#pragma unroll
+        for (int r = 0; r < NPX; ++r) col[r] = 0.f;
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+          if (owner[t] == t) col[ra[t]] = v[t];
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int kk = 0; kk < C::SUB * EMC; kk += 4) {
+      const int kx = kk + kq;
+      const int b = pass + kx / EMC, cc = kx % EMC;
+      float at[TPX], ay[TRX];
+#pragma unroll
+      for (int i = 0; i < TPX; ++i) at[i] = tc[kx * NPX + 16 * i + r16];
+#pragma unroll
+      for (int i = 0; i < TRX; ++i) {
+        const int row = 16 * i + r16;
+        ay[i] = row < EMR ? (SIDE == 1 ? ys[b * C::YS + cc * M1 + row] : ys[b * C::YS + cc + M1 * row]) : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < TPX; ++i)
+#pragma unroll
+        for (int j = 0; j < TPX; ++j) accP[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(at[i], at[j], accP[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < TRX; ++i)
+#pragma unroll
+        for (int j = 0; j < TPX; ++j) accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ay[i], at[j], accR[i][j], 0, 0, 0);
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int i = 0; i < TPX; ++i)
+#pragma unroll
+    for (int j = 0; j < TPX; ++j) acc[(i * TPX + j) * kWave] = accP[i][j];
+#pragma unroll
+  for (int i = 0; i < TRX; ++i)
+#pragma unroll
+    for (int j = 0; j < TPX; ++j) acc[(TPX * TPX + i * TPX + j) * kWave] = accR[i][j];
+}
 
 template <class C>
 __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE)))
@@ -119,9 +211,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
   const int64_t ngroups = (nsig + kSigs - 1) / kSigs;
   float* ys = sY[wv];
   const int eside = a.sums_side;
-  const int ena = eside == 2 ? N2 : N1, emr = eside == 2 ? M2 : M1, emc = eside == 2 ? M1 : M2;
-  const float* eDo = eside == 2 ? sD1 : sD2;
-  const int eld = eside == 2 ? C::LD1 : C::LD2;
+  const int ena = eside == 2 ? N2 : N1, emr = eside == 2 ? M2 : M1;
   f32x4* acc = reinterpret_cast<f32x4*>(sAcc[wv]) + lane;
 #pragma unroll
   for (int q = 0; q < C::NTILE; ++q) acc[q * kWave] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -366,65 +456,10 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
         racc += (double)rr;
       }
     }
-    if (eside) {
-      const int r16 = lane % 16, kq = lane / 16;
-      float* tc = sWork[wv];
-      f32x4 accP[C::TPX][C::TPX], accR[C::TRX][C::TPX];
-#pragma unroll
-      for (int i = 0; i < C::TPX; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TPX; ++j) accP[i][j] = acc[(i * C::TPX + j) * kWave];
-#pragma unroll
-      for (int i = 0; i < C::TRX; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TPX; ++j) accR[i][j] = acc[(C::TPX * C::TPX + i * C::TPX + j) * kWave];
-#pragma unroll
-      for (int pass = 0; pass < kSigs; pass += C::SUB) {
-        if (g >= pass && g < pass + C::SUB) {
-          for (int cc = c; cc < emc; cc += kLanes) {
-            float* col = tc + ((g - pass) * emc + cc) * C::NPX;
-            for (int r = 0; r < C::NPX; ++r) col[r] = 0.f;
-#pragma unroll
-            for (int t = 0; t < S; ++t) {
-              const int ra = eside == 1 ? ia[t] : ja[t], rb = eside == 1 ? ja[t] : ia[t];
-              col[ra] += x[t] * eDo[cc + eld * rb];
-            }
-          }
-        }
-        wave_sync();
-        for (int kk = 0; kk < C::SUB * emc; kk += 4) {
-          const int kx = kk + kq;
-          const int b = pass + kx / emc, cc = kx % emc;
-          float at[C::TPX], ay[C::TRX];
-#pragma unroll
-          for (int i = 0; i < C::TPX; ++i) at[i] = tc[kx * C::NPX + 16 * i + r16];
-#pragma unroll
-          for (int i = 0; i < C::TRX; ++i) {
-            const int row = 16 * i + r16;
-            ay[i] = row < emr ? (eside == 1 ? ys[b * C::YS + cc * M1 + row] : ys[b * C::YS + cc + M1 * row]) : 0.f;
-          }
-#pragma unroll
-          for (int i = 0; i < C::TPX; ++i)
-#pragma unroll
-            for (int j = 0; j < C::TPX; ++j)
-              accP[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(at[i], at[j], accP[i][j], 0, 0, 0);
-#pragma unroll
-          for (int i = 0; i < C::TRX; ++i)
-#pragma unroll
-            for (int j = 0; j < C::TPX; ++j)
-              accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ay[i], at[j], accR[i][j], 0, 0, 0);
-        }
-        wave_sync();
-      }
-#pragma unroll
-      for (int i = 0; i < C::TPX; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TPX; ++j) acc[(i * C::TPX + j) * kWave] = accP[i][j];
-#pragma unroll
-      for (int i = 0; i < C::TRX; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TPX; ++j) acc[(C::TPX * C::TPX + i * C::TPX + j) * kWave] = accR[i][j];
-    }
+    if (eside == 1)
+      sums_epilogue<C, 1>(acc, sWork[wv], ys, sD2, x, ia, ja, g, c, lane);
+    else if (eside == 2)
+      sums_epilogue<C, 2>(acc, sWork[wv], ys, sD1, x, ia, ja, g, c, lane);
     wave_sync();
   }
   if (eside) {
