@@ -135,7 +135,7 @@ __device__ inline void sums_epilogue(f32x4* acc, float* tc, const float* ys, con
       }
     }
     wave_sync();
-#pragma unroll
+#pragma unroll 2
     for (int kk = 0; kk < C::SUB * EMC; kk += 4) {
       const int kx = kk + kq;
       const int b = pass + kx / EMC, cc = kx % EMC;
