@@ -8,7 +8,8 @@
 // (lane l supplies A[l%16][8(l/16)..8(l/16)+7] and B[8(l/16)..+7][l%16]; result v of
 // lane l is D[4(l/16)+v][l%16]), or 16x16x4 FP32 MFMA in the FP32 check mode.
 // Workgroup tile 64x64x32 staged through LDS in K-contiguous layout, four waves of
-// 32x32.  Epilogues are fused: bias + exact-erf GELU (keeping the pre-activation for
+// 32x32 (all operand layouts, FP32 or BF16); the BF16 forward layers use a 128x128
+// tile kernel with register-prefetched 16-byte loads.  Epilogues are fused: bias + exact-erf GELU (keeping the pre-activation for
 // the backward pass), multiplication by GELU'(z) when back-propagating, FP32 store.
 #include <hip/hip_bf16.h>
 #include <math.h>
@@ -20,6 +21,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 32, KP = BK + 8;  // LDS row length (16-byte aligned, bank spread)
 
@@ -134,6 +136,129 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       }
 }
 
+// BF16 C = A B^T (A: M x K activations, row-major; B: N x K weights, row-major) for the
+// forward layers.  Each MFMA operand fragment (one row, 8 consecutive k) is 16 contiguous
+// bytes of A or B, so lanes load their fragments straight from global memory into
+// registers (no LDS, no barriers), four K slices in flight.  Workgroup tile 128 x 128,
+// four waves of 64 x 64 (4 x 4 MFMA 16x16x32 tiles), rows >= M masked.  Same epilogues as
+// gemm_kernel.
+constexpr int TM = 128, TN = 128, TK = 32;
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
+
+__global__ void __launch_bounds__(256) gemm_nt_bf16_kernel(GemmArgs g) {
+  const __bf16* A = static_cast<const __bf16*>(g.A);
+  const __bf16* B = static_cast<const __bf16*>(g.B);
+  const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  // workgroups are dealt round-robin to the 8 XCDs (each with its own L2): give each XCD a
+  // contiguous run of tiles, so the N tiles of one row panel of A share an L2
+  const int ntn = gridDim.x, ntiles = gridDim.x * gridDim.y;
+  const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+  int tile = lin;
+  if (ntiles % kXcds == 0) tile = (lin % kXcds) * (ntiles / kXcds) + lin / kXcds;
+  const int m0 = (tile / ntn) * TM, n0 = (tile % ntn) * TN;
+  const int wm = (w / 2) * 64, wn = (w % 2) * 64;
+  const int r16 = lane % 16, kq = lane / 16;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const __bf16* pa[4];
+  const __bf16* pb[4];
+  bool va[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + wm + 16 * i + r16;
+    va[i] = m < g.M;
+    pa[i] = A + (size_t)(va[i] ? m : 0) * g.lda + 8 * kq;
+    pb[i] = B + (size_t)(n0 + wn + 16 * i + r16) * g.ldb + 8 * kq;
+  }
+  auto load = [&](bf16x8 (&a)[4], bf16x8 (&b)[4], int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = *reinterpret_cast<const bf16x8*>(pa[i] + k0);
+      if (!va[i]) a[i] = bf16x8{};
+      b[i] = *reinterpret_cast<const bf16x8*>(pb[i] + k0);
+    }
+  };
+  auto mma = [&](const bf16x8 (&a)[4], const bf16x8 (&b)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  };
+  // four K slices in flight per wave (the global-load latency is several times one
+  // slice's MFMA work); stage indices are static after unrolling by four
+  constexpr int NS = 4;
+  bf16x8 a[NS][4], b[NS][4];
+  const int nk = g.K / TK;
+#pragma unroll
+  for (int u = 0; u < NS - 1; ++u)
+    if (u < nk) load(a[u], b[u], u * TK);
+  for (int ks = 0; ks < nk; ks += NS) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int k = ks + u;
+      if (k < nk) {
+        if (k + NS - 1 < nk) load(a[(u + NS - 1) % NS], b[(u + NS - 1) % NS], (k + NS - 1) * TK);
+        mma(a[u], b[u]);
+      }
+    }
+  }
+  // epilogue through LDS, 32 rows of the wave's 64 x 64 tile at a time: the raw sums go in
+  // in the MFMA layout and come out as runs of 4 consecutive columns, where bias, GELU /
+  // GELU' and the conversion are applied and every store is a contiguous 8- or 16-byte chunk
+  __shared__ __align__(16) float stile[4][32][64 + 4];
+  float(*st)[68] = stile[w];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) st[16 * i + 4 * kq + v][16 * j + r16] = acc[2 * h + i][j][v];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = lane + 64 * u, r = e / 16, c4 = 4 * (e % 16);
+      const int m = m0 + wm + 32 * h + r, n = n0 + wn + c4;
+      if (m >= g.M) continue;
+      const float4 x = *reinterpret_cast<const float4*>(&st[r][c4]);
+      const size_t o = (size_t)m * g.ldc + n;
+      float y[4] = {x.x, x.y, x.z, x.w};
+      if (g.epi == kEpiStoreF32) {
+        if (g.bias) {
+          const float4 b = *reinterpret_cast<const float4*>(g.bias + n);
+          y[0] += b.x; y[1] += b.y; y[2] += b.z; y[3] += b.w;
+        }
+        *reinterpret_cast<float4*>(static_cast<float*>(g.C) + o) = make_float4(y[0], y[1], y[2], y[3]);
+      } else {
+        if (g.epi == kEpiBiasGelu) {
+          const float4 b = *reinterpret_cast<const float4*>(g.bias + n);
+          y[0] += b.x; y[1] += b.y; y[2] += b.z; y[3] += b.w;
+          if (g.Z) *reinterpret_cast<float4*>(g.Z + o) = make_float4(y[0], y[1], y[2], y[3]);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) y[q] = gelu(y[q]);
+        } else {  // kEpiGeluGrad
+          const float4 z = *reinterpret_cast<const float4*>(g.Z + o);
+          y[0] *= gelu_grad(z.x); y[1] *= gelu_grad(z.y); y[2] *= gelu_grad(z.z); y[3] *= gelu_grad(z.w);
+        }
+        __bf16* co = static_cast<__bf16*>(g.C) + o;
+        bf16x4 ov;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ov[q] = (__bf16)y[q];
+        *reinterpret_cast<bf16x4*>(co) = ov;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // X[b][p] = Y_{idx(b)}[p] / ||Y_{idx(b)}||_F in the compute type (vec order = column-major)
 template <typename T>
 __global__ void prep_input_kernel(const float* Y, const int32_t* idx, int64_t B, int M, T* X, float* ynorm2) {
@@ -227,6 +352,14 @@ __global__ void copy_params_kernel(const float* p, T* pc, int64_t n) {
 
 template <typename T>
 hipError_t launch_gemm(const GemmArgs& g, int opA, int opB, hipStream_t st) {
+  const bool aligned = ((reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B) |
+                         reinterpret_cast<uintptr_t>(g.C) | reinterpret_cast<uintptr_t>(g.Z) |
+                         reinterpret_cast<uintptr_t>(g.bias)) & 15u) == 0;
+  if (sizeof(T) == 2 && opA == 0 && opB == 1 && aligned && g.N % TN == 0 && g.K % TK == 0 && g.lda % 8 == 0 &&
+      g.ldb % 8 == 0 && g.ldc % 4 == 0) {
+    hipLaunchKernelGGL(gemm_nt_bf16_kernel, dim3(g.N / TN, (g.M + TM - 1) / TM), dim3(256), 0, st, g);
+    return hipGetLastError();
+  }
   const dim3 grid(g.N / BN, g.M / BM);
   if (opA == 0 && opB == 1) hipLaunchKernelGGL((gemm_kernel<T, 0, 1>), grid, dim3(256), 0, st, g);
   else if (opA == 0 && opB == 0) hipLaunchKernelGGL((gemm_kernel<T, 0, 0>), grid, dim3(256), 0, st, g);

@@ -101,6 +101,22 @@ def test_logits_and_proposal_fp32(rng):
     np.testing.assert_allclose(pr.res2.cpu().double().numpy(), rref, rtol=1e-2, atol=1e-5)
 
 
+def test_logits_bf16(rng):
+    """BF16 forward (the 128x128 tile kernel; 320 rows, so the last tile is half full) against
+    the FP64 oracle: BF16 operands with FP32 accumulation, bar 2e-2 of the largest logit."""
+    H = 512
+    p = weights(rng, H)
+    Y, supp, _, _ = data(rng, 320)
+    net = api.Proposer(M1, M2, N1, N2, hidden=H)
+    net.set_params(p)
+    Yd, _ = to_dev(Y, supp)
+    z = net.logits(Yd).cpu().numpy()
+    zref, _ = mlp.forward(p.astype(np.float64), mlp.inputs(Y), 64, H, 256)
+    err = np.max(np.abs(z - zref)) / np.max(np.abs(zref))
+    print("bf16 logits max rel err %.2e" % err)
+    assert err <= 2e-2
+
+
 def test_all_rejected_equals_plain_omp(rng):
     Y, _, d1, d2 = data(rng, 1000)
     net = api.Proposer(M1, M2, N1, N2, hidden=128)
