@@ -336,10 +336,12 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
 #pragma unroll
       for (int k = 0; k < t; ++k) stop = stop || (ba == ia[k] + N1 * ja[k]);
       if (stop) active = false;
+      // The step runs in every lane (a stopped signal computes values it never commits), so
+      // the common path has no branches: results are committed with selects below.
       float w[S > 1 ? S - 1 : 1];
-      float d2 = 0.f, gaa = 1.f;
-      if (active) {
-        gaa = sG1[it + N1 * it] * sG2[jt + N2 * jt];
+      const float gaa = sG1[it + N1 * it] * sG2[jt + N2 * jt];
+      float d2;
+      {
         float ww = 0.f;
 #pragma unroll
         for (int k = 0; k < t; ++k) {
@@ -350,7 +352,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
           ww += w[k] * w[k];
         }
         d2 = gaa - ww;
-        if (d2 < piv * gaa) {
+        if (active && d2 < piv * gaa) {
           double w64[S > 1 ? S - 1 : 1];
           double accd = 0.0;
 #pragma unroll
@@ -384,7 +386,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
 #pragma unroll
         for (int k = 0; k < t; ++k) cor -= sG1[ia[k] + N1 * it] * sG2[ja[k] + N2 * jt] * x[k];
       }
-      if (active) {
+      {
         float vv[S > 1 ? S - 1 : 1];
 #pragma unroll
         for (int k = t - 1; k >= 0; --k) {
@@ -394,16 +396,17 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
           vv[k] = b * dinv[k];
         }
         const float cst = cor / d2;
+        // the signal's four lanes write the same row: no divergent store
 #pragma unroll
         for (int k = 0; k < t; ++k) {
-          if (c == 0) L[tri(t, k)] = w[k];
-          x[k] -= cst * vv[k];
+          L[tri(t, k)] = w[k];
+          x[k] = active ? x[k] - cst * vv[k] : x[k];
         }
         dinv[t] = rsqrtf(d2);
-        x[t] = cst;
-        ia[t] = it;
-        ja[t] = jt;
-        nsel = t + 1;
+        x[t] = active ? cst : 0.f;
+        ia[t] = active ? it : 0;
+        ja[t] = active ? jt : 0;
+        nsel = active ? t + 1 : nsel;
         if (t + 1 < S) {
           // corr += sum_k (-gamma_k G1[:, i_k]) (x) G2[j_k, :], gamma_t = cst, gamma_k = -cst v_k
 #pragma unroll
