@@ -247,9 +247,11 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
       for (int k = 0; k < t; ++k) stop = stop || (ba == ia[k] + N1 * ja[k]);
       if (stop) active = false;
       const int it = ba % N1, jt = ba / N1;
+      // The step runs in every lane (a stopped signal computes values it never commits), so
+      // the common path has no branches: results are committed with selects below.
       float w[S > 1 ? S - 1 : 1];
-      float d2 = 0.f;
-      if (active) {
+      float d2;
+      {
         const float gaa = sG1[it + N1 * it] * sG2[jt + N2 * jt];
         float ww = 0.f;
 #pragma unroll
@@ -261,7 +263,7 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
           ww += w[k] * w[k];
         }
         d2 = gaa - ww;
-        if (d2 < piv * gaa) {
+        if (active && d2 < piv * gaa) {
           // small pivot: this row again in FP64
           double w64[S > 1 ? S - 1 : 1];
           double acc = 0.0;
@@ -280,7 +282,7 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
         }
         if (!(d2 > dep_eps * gaa)) active = false;
       }
-      if (active) {
+      {
         // v = L^{-T} w ; coefficients x_S -= c v, x_t = c with c = corr_a / delta^2
         float v[S > 1 ? S - 1 : 1];
 #pragma unroll
@@ -291,16 +293,17 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
           v[k] = b * dinv[k];
         }
         const float cst = bs / d2;
+        // every lane of the group writes the same row: no divergent store
 #pragma unroll
         for (int k = 0; k < t; ++k) {
-          if (sub == 0) L[tri(t, k)] = w[k];
-          x[k] -= cst * v[k];
+          L[tri(t, k)] = w[k];
+          x[k] = active ? x[k] - cst * v[k] : x[k];
         }
         dinv[t] = rsqrtf(d2);
-        x[t] = cst;
-        ia[t] = it;
-        ja[t] = jt;
-        nsel = t + 1;
+        x[t] = active ? cst : 0.f;
+        ia[t] = active ? it : 0;
+        ja[t] = active ? jt : 0;
+        nsel = active ? t + 1 : nsel;
         if (t + 1 < S) {
           // corr <- corr - c * (G_{:,a} - G_{:,S} v): t+1 rank-one terms gamma_k g1_k g2_k^T
 #pragma unroll
