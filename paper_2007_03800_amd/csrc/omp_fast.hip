@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
           }
         }
       }
-      wave_sync();
+      // no wave sync here: each lane reads back only the L rows it wrote itself
     }
 
     // ---- explicit residual and outputs

@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
           }
         }
       }
-      wave_sync();
+      // no wave sync here: each lane reads back only the L rows it wrote itself
     }
 
     // ---- explicit residual and outputs
