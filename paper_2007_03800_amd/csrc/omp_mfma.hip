@@ -9,7 +9,8 @@
 //    the 4x4x1 16-block FP32 MFMA (block = signal, lane c of the block holds column c
 //    of each tile), so each rank-one refresh term gamma_k G1[:,i_k] G2[j_k,:] of the
 //    Gram-form update is one MFMA per tile, and the first correlation
-//    C = D1^T (Y D2) is eight more rank-one terms.
+//    C = D1^T (Y D2) is m1 more rank-one terms, with Y D2 itself formed in the same
+//    layout (m2 rank-one terms per 4x4 tile).
 //  * Largest |corr| search on packed keys: |corr| with its low 6 mantissa bits
 //    replaced by the element's position inside the lane, reduced with 3-input max
 //    and two DPP quad permutes.  Correlations within 2^-17 relative of each other
@@ -54,7 +55,7 @@ struct MCfg {
   static constexpr int STAGE = kSigs * YS > NENTX ? kSigs * YS : NENTX;
   static_assert(N1 % 4 == 0 && N2 % 4 == 0, "4x4 tiles");
   static_assert(NT * 4 <= 64, "at most 64 correlations per lane (6-bit position in the keys)");
-  static_assert(M % 4 == 0 && M2 % kLanes == 0, "staging and lane split of the first correlation");
+  static_assert(M % 4 == 0 && M1 % 4 == 0 && M2 % kLanes == 0, "staging and 4x4 tiles of Y D2");
 };
 
 __device__ inline void wave_sync() {
@@ -252,25 +253,39 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
     f32x4 al[NT];
 #pragma unroll
     for (int q = 0; q < NT; ++q) al[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // V = Y D2 on the matrix cores, in 4x4 tiles (rows 4bp + v, columns 4bj + c): lane c
+    // supplies Y[4bp + c, q] and D2[q, 4bj + c] for each rank-one term q.  Register v of tile
+    // (bp, bj) in lane c is then V[4bp + v, 4bj + c], exactly the B operand the second stage
+    // C = D1^T V needs for row p = 4bp + v.
+    f32x4 vt[M1 / 4][TJ];
+#pragma unroll
+    for (int bp = 0; bp < M1 / 4; ++bp)
+#pragma unroll
+      for (int bj = 0; bj < TJ; ++bj) vt[bp][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < M2; ++q) {
+      float ya[M1 / 4], db[TJ];
+#pragma unroll
+      for (int bp = 0; bp < M1 / 4; ++bp) ya[bp] = y[(4 * bp + c) + M1 * q];
+#pragma unroll
+      for (int bj = 0; bj < TJ; ++bj) db[bj] = sD2[q + C::LD2 * (4 * bj + c)];
+#pragma unroll
+      for (int bp = 0; bp < M1 / 4; ++bp)
+#pragma unroll
+        for (int bj = 0; bj < TJ; ++bj)
+          vt[bp][bj] = __builtin_amdgcn_mfma_f32_4x4x1f32(ya[bp], db[bj], vt[bp][bj], 0, 0, 0);
+    }
 #pragma unroll
     for (int p = 0; p < M1; ++p) {
-      // V[p][4bj + c] = sum_q Y[p,q] D2[q, 4bj + c]
-      float vb[TJ];
-#pragma unroll
-      for (int bj = 0; bj < TJ; ++bj) vb[bj] = 0.f;
-#pragma unroll
-      for (int q = 0; q < M2; ++q) {
-        const float yv = y[p + M1 * q];
-#pragma unroll
-        for (int bj = 0; bj < TJ; ++bj) vb[bj] += yv * sD2[q + C::LD2 * (4 * bj + c)];
-      }
       const float* d1p = sD1P + p * N1 + c * TI;  // D1[p, 4bi + c]
 #pragma unroll
       for (int bi = 0; bi < TI; ++bi) {
         const float av = d1p[bi];
 #pragma unroll
-        for (int bj = 0; bj < TJ; ++bj)
-          al[bi * TJ + bj] = __builtin_amdgcn_mfma_f32_4x4x1f32(av, vb[bj], al[bi * TJ + bj], 0, 0, 0);
+        for (int bj = 0; bj < TJ; ++bj) {
+          const float vb = vt[p / 4][bj][p % 4];  // by value (see the argmax keys)
+          al[bi * TJ + bj] = __builtin_amdgcn_mfma_f32_4x4x1f32(av, vb, al[bi * TJ + bj], 0, 0, 0);
+        }
       }
     }
 
