@@ -124,13 +124,24 @@ def learned_vs_plain(args, api, oracle, synth):
         api.learn(pr, K, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        _, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+        s_o, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
         r_g = pr.res2[:nsub].double().cpu().numpy()
         out[name + "_value"] = nev * K / dt
         out[name + "_rmse_vs_oracle"] = float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean()))
+        out[name + "_support_agreement"] = support_agreement(pr.supp[:nsub].cpu().numpy(), s_o)["support_agreement"]
     out["unit"] = "signals/s per iteration"
     out["learned_over_plain"] = out["learned_value"] / out["plain_value"]
     return out
+
+
+def support_agreement(supp_gpu, supp_oracle):
+    """Fraction of signals whose support set equals the oracle's, and fraction of the oracle's
+    chosen atoms that the GPU also chose (empty slots are -1 on both sides)."""
+    g = np.sort(np.asarray(supp_gpu, np.int64), axis=1)
+    o = np.sort(np.asarray(supp_oracle, np.int64), axis=1)
+    same = float(np.mean(np.all(g == o, axis=1)))
+    hit = ((g[:, :, None] == o[:, None, :]) & (o[:, None, :] >= 0)).any(axis=1).sum()
+    return {"support_agreement": same, "atom_agreement": float(hit / max(1, int((o >= 0).sum())))}
 
 
 def device_signals(synth, w, dtype, k0=0, k1=None, chunk=100_000):
@@ -182,12 +193,13 @@ def mixed_workload(api, oracle, synth):
     pr, trace, dt = timed_learn(api, fresh, w.iters)
     nsub = 5000
     Ysub = Y[:nsub].double().cpu().numpy().transpose(0, 2, 1)  # the rounded signals, math layout
-    _, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+    s_o, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
     r_g = pr.res2[:nsub].double().cpu().numpy()
     return {"workload": w.name, "N": w.N, "steps": w.iters, "dtype": "bf16 signals, f32 arithmetic, f64 solves",
             "value": w.N * w.iters / dt, "unit": "signals/s per iteration", "ms_per_step": dt / w.iters * 1e3,
             "rmse_first": float(trace[0][0]), "rmse_final": float(trace[0][-1]),
-            "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())), "omp_kernel": kernel_name(api, w)}
+            "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
+            **support_agreement(pr.supp[:nsub].cpu().numpy(), s_o), "omp_kernel": kernel_name(api, w)}
 
 
 def uneven_workload(api, oracle, synth):
@@ -209,10 +221,11 @@ def uneven_workload(api, oracle, synth):
     for w, pr, tr in zip(ws, probs, trace):
         nsub = 2000
         Ysub = synth.signals(w, 0, nsub)
-        _, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+        s_o, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
         r_g = pr.res2[:nsub].double().cpu().numpy()
         per.append({"workload": w.name, "N": w.N, "rmse_final": float(tr[-1]),
                     "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
+                    **support_agreement(pr.supp[:nsub].cpu().numpy(), s_o),
                     "omp_kernel": kernel_name(api, w)})
     return {"N": ntot, "steps": K, "value": ntot * K / dt, "unit": "signals/s per iteration",
             "ms_per_step": dt / K * 1e3, "problems": per}
@@ -297,9 +310,10 @@ def main():
     # matched RMSE: the oracle's 2D-OMP at the final GPU dictionaries on a 5000-signal prefix
     nsub = min(5000, w.N)
     Ysub = synth.signals(w, 0, nsub)
-    _, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+    s_o, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
     r_g = pr.res2[:nsub].double().cpu().numpy()
     rmse_ratio = float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean()))
+    agree = support_agreement(pr.supp[:nsub].cpu().numpy(), s_o)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -358,6 +372,7 @@ def main():
         "kernel_avg_ms": per_class,
         "rmse_final": float(trace[-1]),
         "rmse_vs_oracle": rmse_ratio,
+        **agree,
         "learned_vs_plain": learned,
         "mixed_precision": mixed,
         "uneven_batch": uneven,
