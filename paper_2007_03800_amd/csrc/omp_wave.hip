@@ -9,10 +9,15 @@
 //    i = sr + LR*ri, j = sc + LC*cj in E = (n1/LR)(n2/LC) registers, so each Gram-form
 //    refresh term gamma_k G1[:, i_k] G2[j_k, :] is an E-element rank-one update from
 //    NRI + NCJ contiguous LDS reads.
-//  * The support, coefficients, Cholesky pivots and the triangular solves are spread
-//    over lanes (lane k holds element k of the support): each solve step broadcasts one
-//    value with readlane and updates the remaining lanes, so a step costs a few
-//    instructions instead of a serial loop in every lane.  The Cholesky rows sit in LDS.
+//  * The least squares is carried by the inverse of the Cholesky factor, L^{-1}, kept
+//    in LDS (packed rows with the diagonal).  Appending atom a with Gram column g = G_{S,a}
+//    needs w = L^{-1} g (the new row of L), v = L^{-T} w and delta^2 = G_aa - |w|^2; the
+//    new row of L^{-1} is [-v^T, 1] / delta.  Both products are matrix-vector products
+//    spread over lanes (lane k holds element k of the support, its coefficient and its
+//    Gram entry), so a step has no serial triangular solve.
+//  * Each step writes the refresh coefficients gamma_q and the support atoms to LDS; the
+//    refresh reads them four terms at a time (padding terms have gamma = 0), so their
+//    LDS latencies overlap.
 //  * Loops over the greedy step and the support are runtime loops: code size does not
 //    grow with s.  Chosen atoms are masked explicitly (one bit per register element),
 //    as in the generic kernel and the FP64 reference.
@@ -33,15 +38,19 @@ template <int M1_, int M2_, int N1_, int N2_, int S_, int LR_, int LC_>
 struct WCfg {
   static constexpr int M1 = M1_, M2 = M2_, N1 = N1_, N2 = N2_, S = S_, LR = LR_, LC = LC_;
   static constexpr int LG = LR * LC, NRI = N1 / LR, NCJ = N2 / LC, E = NRI * NCJ;
-  static constexpr int M = M1 * M2, NL = S * (S - 1) / 2 + 1;  // strictly lower rows of L
-  static constexpr int WS = N1 * M2;                             // first-correlation staging
-  static constexpr int PW = M + WS + NL + 1;                     // per-wave LDS words (+1: odd stride)
+  static constexpr int M = M1 * M2;
+  static constexpr int NLI = S * (S + 1) / 2;   // packed rows of L^{-1} with the diagonal
+  static constexpr int SP = (S + 2 + 3) / 4 * 4;  // support arrays, padded for 4-term batches
+  static constexpr int WS = N1 * M2;            // first-correlation staging
+  static constexpr int PW = M + WS + NLI + 5 * SP + 1;  // per-wave LDS words (+1: odd stride)
+  // occupancy target (waves per SIMD) that bounds the registers of the 4-term refresh
+  static constexpr int WPE = E <= 16 ? 4 : (E <= 32 ? 3 : 2);
   static_assert(N1 % LR == 0 && N2 % LC == 0 && LG <= 64, "lane grid must tile the atoms");
   static_assert(E <= 64, "one mask bit per register element");
   static_assert(S <= LG, "support element k lives in lane k of the grid");
 };
 
-constexpr int tril(int k, int l) { return k * (k - 1) / 2 + l; }  // L[k][l], l < k
+constexpr int trow(int k) { return k * (k + 1) / 2; }  // row k of packed L^{-1}
 
 template <typename U>
 __device__ inline U bcast(U v, int k) {  // value of lane k (k uniform)
@@ -68,24 +77,9 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Forward solve L w = b for the new Cholesky row, in precision U, with the support
-// spread over lanes: lane k < t holds b_k (= G_{k,a}) and dinv_k; returns w_k in lane k
-// and |w|^2 in every lane.  Lrow: packed strictly-lower rows of L (tril).
-template <typename U, typename T>
-__device__ inline U forward_row(U b, U dinv, const T* Lrow, int t, int lane, U& ww) {
-  U w = 0;
-  ww = 0;
-  for (int k = 0; k < t; ++k) {
-    const U wk = bcast(b, k) * bcast(dinv, k);
-    ww += wk * wk;
-    if (lane == k) w = wk;
-    if (lane > k && lane < t) b -= (U)Lrow[tril(lane, k)] * wk;
-  }
-  return w;
-}
-
 template <typename T, class C>
-__global__ void __launch_bounds__(kWave* kWaveWaves) omp_wave_kernel(OmpArgs<T> a) {
+__global__ void __launch_bounds__(kWave* kWaveWaves)
+    omp_wave_kernel(OmpArgs<T> a) {
   constexpr int M1 = C::M1, M2 = C::M2, N1 = C::N1, N2 = C::N2, S = C::S, LR = C::LR;
   constexpr int NRI = C::NRI, NCJ = C::NCJ, E = C::E, M = C::M;
   __shared__ T sD1[M1 * N1];                  // D1[p, i] at p + M1 i
@@ -111,7 +105,12 @@ __global__ void __launch_bounds__(kWave* kWaveWaves) omp_wave_kernel(OmpArgs<T> 
   const int sr = lane % LR, sc = (lane / LR) % C::LC;
   T* ys = sW[wv];
   T* Ws = ys + M;
-  T* Lrow = Ws + C::WS;
+  T* Li = Ws + C::WS;        // L^{-1}, packed rows with the diagonal
+  T* gam = Li + C::NLI;      // refresh coefficients gamma_q (zero beyond the support)
+  T* supi = gam + C::SP;     // support atoms i_q, j_q (exact small integers)
+  T* supj = supi + C::SP;
+  T* xg = supj + C::SP;      // exchange vectors: Gram column g, then w
+  T* xw = xg + C::SP;
   // G1[i, i'] and G2[j, j'] from the permuted tables (both are symmetric)
   auto g1 = [&](int i, int ik) { return sG1P[ik * N1 + (i % LR) * NRI + i / LR]; };
   auto g2 = [&](int jk, int j) { return sG2P[jk * N2 + (j % C::LC) * NCJ + j / C::LC]; };
@@ -133,40 +132,54 @@ __global__ void __launch_bounds__(kWave* kWaveWaves) omp_wave_kernel(OmpArgs<T> 
       Ws[e] = v;
     }
     wave_sync();
+    // C[i, j] = sum_q W[i, q] D2[q, j] as m2 rank-one updates of the lane's block: the
+    // live set stays at the block plus one column and one row
     T corr[E];
 #pragma unroll
-    for (int ri = 0; ri < NRI; ++ri)
+    for (int e = 0; e < E; ++e) corr[e] = 0;
+    if (act) {
+#pragma unroll 2
+      for (int q = 0; q < M2; ++q) {
+        T wi[NRI];
 #pragma unroll
-      for (int cj = 0; cj < NCJ; ++cj) {
-        T v = 0;
-        if (act) {
-          const int i = sr + LR * ri, j = sc + C::LC * cj;
-          for (int q = 0; q < M2; ++q) v += Ws[i + N1 * q] * sD2[q + M2 * j];
+        for (int ri = 0; ri < NRI; ++ri) wi[ri] = Ws[(sr + LR * ri) + N1 * q];
+#pragma unroll
+        for (int cj = 0; cj < NCJ; ++cj) {
+          const T d = sD2[q + M2 * (sc + C::LC * cj)];
+#pragma unroll
+          for (int ri = 0; ri < NRI; ++ri) corr[ri * NCJ + cj] += wi[ri] * d;
         }
-        corr[ri * NCJ + cj] = v;
       }
+    }
+    for (int e = lane; e < 3 * C::SP; e += kWave) gam[e] = 0;  // gam, supi, supj
+    wave_sync();
     unsigned long long used = 0ull;  // bit e: register element e is a chosen atom
     // support element k lives in lane k
-    T my_x = 0, my_dinv = 0;
+    T my_x = 0;
     int my_i = 0, my_j = 0;
     int t = 0;
     bool early = false;
     const T stop_thr = (T)a.stop_rel * ynorm;
+#pragma unroll 1
     for (; t < S; ++t) {
-      // largest |corr| over the unselected atoms; ties to the smaller atom index
+      // largest |corr| over the unselected atoms; ties to the smaller atom index.  A lane
+      // scans its atoms in increasing index order (cj, then ri), so a strict comparison
+      // keeps the first of equal values.
       T bv = T(-1), bs = 0;
       int ba = INT_MAX;
       if (act) {
+        const int base = sr + N1 * sc;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int ri = e / NCJ, cj = e % NCJ;
-          const int at = (sr + LR * ri) + N1 * (sc + C::LC * cj);
-          const T v = fabs(corr[e]);
-          const bool take = !((used >> e) & 1ull) && (v > bv || (v == bv && at < ba));
-          bv = take ? v : bv;
-          bs = take ? corr[e] : bs;
-          ba = take ? at : ba;
-        }
+        for (int cj = 0; cj < NCJ; ++cj)
+#pragma unroll
+          for (int ri = 0; ri < NRI; ++ri) {
+            const int e = ri * NCJ + cj;
+            const T v = fabs(corr[e]);
+            const bool take = !((used >> e) & 1ull) && v > bv;
+            bv = take ? v : bv;
+            bs = take ? corr[e] : bs;
+            ba = take ? base + LR * ri + N1 * C::LC * cj : ba;
+          }
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
@@ -183,16 +196,47 @@ __global__ void __launch_bounds__(kWave* kWaveWaves) omp_wave_kernel(OmpArgs<T> 
       }
       const int ia = ba % N1, ja = ba / N1;
       const T gaa = g1(ia, ia) * g2(ja, ja);
-      const T bk = lane < t ? g1(my_i, ia) * g2(ja, my_j) : T(0);
-      T ww;
-      T w = forward_row<T, T>(bk, my_dinv, Lrow, t, lane, ww);
+      // w = L^{-1} g, lane k < t taking row k
+      if (lane < t) xg[lane] = g1(my_i, ia) * g2(ja, my_j);
+      wave_sync();
+      T w = 0;
+      if (lane < t) {
+        const T* row = Li + trow(lane);
+        T p0 = 0, p1 = 0;
+        int l = 0;
+        for (; l + 1 <= lane; l += 2) {
+          p0 += row[l] * xg[l];
+          p1 += row[l + 1] * xg[l + 1];
+        }
+        if (l <= lane) p0 += row[l] * xg[l];
+        w = p0 + p1;
+        xw[lane] = w;
+      }
+      wave_sync();
+      // |w|^2 in every lane, v = L^{-T} w in lane l < t (column l of L^{-1})
+      T ww = 0, v = 0;
+#pragma unroll 4
+      for (int k = 0; k < t; ++k) {
+        const T wk = xw[k];
+        ww += wk * wk;
+        if (lane <= k) v += Li[trow(k) + lane] * wk;
+      }
       T d2 = gaa - ww;
       if (sizeof(T) == 4 && d2 < (T)a.pivot_fp64 * gaa) {
-        // small pivot: the row again in FP64 (cancellation in G_aa - |w|^2)
-        const double bk64 = lane < t ? (double)g1(my_i, ia) * (double)g2(ja, my_j) : 0.0;
-        double ww64;
-        const double w64 = forward_row<double, T>(bk64, (double)my_dinv, Lrow, t, lane, ww64);
-        w = (T)w64;
+        // small pivot: w and |w|^2 again in FP64 (cancellation in G_aa - |w|^2)
+        double w64 = 0.0;
+        if (lane < t) {
+          const T* row = Li + trow(lane);
+          for (int l = 0; l <= lane; ++l)
+            w64 += (double)row[l] * ((double)g1((int)supi[l], ia) * (double)g2(ja, (int)supj[l]));
+        }
+        const double ww64 = wave_sum(lane < t ? w64 * w64 : 0.0);
+        wave_sync();
+        if (lane < t) xw[lane] = (T)w64;
+        wave_sync();
+        v = 0;
+        for (int k = 0; k < t; ++k)
+          if (lane <= k) v += Li[trow(k) + lane] * xw[k];
         d2 = (T)((double)gaa - ww64);
         if (lane == 0) atomicAdd(&a.counters[kCtrFp64Pivot], 1ull);
       }
@@ -200,42 +244,51 @@ __global__ void __launch_bounds__(kWave* kWaveWaves) omp_wave_kernel(OmpArgs<T> 
         early = true;
         break;
       }
-      // v = L^{-T} w, from the last support element up
-      T c = w, v = 0;
-      for (int q = t - 1; q >= 0; --q) {
-        const T vq = bcast(c, q) * bcast(my_dinv, q);
-        if (lane == q) v = vq;
-        if (lane < q) c -= (T)Lrow[tril(q, lane)] * vq;
-      }
       const T cst = bs / d2;
+      const T dinv = (T)1 / sqrt(d2);
+      T* rowt = Li + trow(t);
       if (lane < t) {
-        Lrow[tril(t, lane)] = w;
+        rowt[lane] = -v * dinv;
         my_x -= cst * v;
+        gam[lane] = cst * v;
       }
       if (lane == t) {
+        rowt[t] = dinv;
         my_x = cst;
         my_i = ia;
         my_j = ja;
-        my_dinv = (T)1 / sqrt(d2);
+        gam[t] = -cst;
+        supi[t] = (T)ia;
+        supj[t] = (T)ja;
       }
       if (act && sr == ia % LR && sc == ja % C::LC) used |= 1ull << ((ia / LR) * NCJ + ja / C::LC);
       wave_sync();
-      if (t + 1 < S) {
-        // corr <- corr - cst (G_{:,a} - G_{:,S} v): terms gamma_q G1[:, i_q] G2[j_q, :]
-        for (int q = 0; q <= t; ++q) {
-          const T gq = q == t ? -cst : cst * bcast(v, q);
-          const int iq = q == t ? ia : bcast(my_i, q), jq = q == t ? ja : bcast(my_j, q);
-          if (!act) continue;
-          const T* p1 = sG1P + iq * N1 + sr * NRI;
-          const T* p2 = sG2P + jq * N2 + sc * NCJ;
-          T u1[NRI];
+      if (t + 1 < S && act) {
+        // corr <- corr - cst (G_{:,a} - G_{:,S} v): terms gamma_q G1[:, i_q] G2[j_q, :],
+        // four at a time (terms beyond t have gamma = 0 and atom 0)
+#pragma unroll 1
+        for (int q0 = 0; q0 <= t; q0 += 4) {
+          T gq[4];
+          int iq[4], jq[4];
 #pragma unroll
-          for (int ri = 0; ri < NRI; ++ri) u1[ri] = gq * p1[ri];
+          for (int u = 0; u < 4; ++u) {
+            gq[u] = gam[q0 + u];
+            iq[u] = (int)supi[q0 + u];
+            jq[u] = (int)supj[q0 + u];
+          }
 #pragma unroll
-          for (int cj = 0; cj < NCJ; ++cj) {
-            const T u2 = p2[cj];
+          for (int u = 0; u < 4; ++u) {
+            const T* p1 = sG1P + iq[u] * N1 + sr * NRI;
+            const T* p2 = sG2P + jq[u] * N2 + sc * NCJ;
+            T u1[NRI];
 #pragma unroll
-            for (int ri = 0; ri < NRI; ++ri) corr[ri * NCJ + cj] += u1[ri] * u2;
+            for (int ri = 0; ri < NRI; ++ri) u1[ri] = gq[u] * p1[ri];
+#pragma unroll
+            for (int cj = 0; cj < NCJ; ++cj) {
+              const T u2 = p2[cj];
+#pragma unroll
+              for (int ri = 0; ri < NRI; ++ri) corr[ri * NCJ + cj] += u1[ri] * u2;
+            }
           }
         }
       }
