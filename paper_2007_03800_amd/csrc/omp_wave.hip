@@ -31,12 +31,14 @@
 namespace sdl {
 namespace {
 
-constexpr int kWaveWaves = 4;  // signals (waves) per workgroup
 constexpr int kWaveMaxBlocks = 4096;
 
-template <int M1_, int M2_, int N1_, int N2_, int S_, int LR_, int LC_>
+// WPB_: signals (waves) per workgroup, chosen per shape so that the dictionary tables
+// shared by a workgroup plus its waves' buffers leave room for as many waves per CU as
+// the registers allow
+template <int M1_, int M2_, int N1_, int N2_, int S_, int LR_, int LC_, int WPB_>
 struct WCfg {
-  static constexpr int M1 = M1_, M2 = M2_, N1 = N1_, N2 = N2_, S = S_, LR = LR_, LC = LC_;
+  static constexpr int M1 = M1_, M2 = M2_, N1 = N1_, N2 = N2_, S = S_, LR = LR_, LC = LC_, WPB = WPB_;
   static constexpr int LG = LR * LC, NRI = N1 / LR, NCJ = N2 / LC, E = NRI * NCJ;
   static constexpr int M = M1 * M2;
   static constexpr int NLI = S * (S + 1) / 2;   // packed rows of L^{-1} with the diagonal
@@ -78,7 +80,7 @@ __device__ inline void wave_sync() {
 }
 
 template <typename T, class C>
-__global__ void __launch_bounds__(kWave* kWaveWaves)
+__global__ void __launch_bounds__(kWave* C::WPB)
     omp_wave_kernel(OmpArgs<T> a) {
   constexpr int M1 = C::M1, M2 = C::M2, N1 = C::N1, N2 = C::N2, S = C::S, LR = C::LR;
   constexpr int NRI = C::NRI, NCJ = C::NCJ, E = C::E, M = C::M;
@@ -86,7 +88,7 @@ __global__ void __launch_bounds__(kWave* kWaveWaves)
   __shared__ T sD2[M2 * N2];                  // D2[q, j] at q + M2 j
   __shared__ __align__(16) T sG1P[N1 * N1];   // [ik][sr][ri] = G1[sr + LR ri, ik]
   __shared__ __align__(16) T sG2P[N2 * N2];   // [jk][sc][cj] = G2[jk, sc + LC cj]
-  __shared__ T sW[kWaveWaves][C::PW];
+  __shared__ T sW[C::WPB][C::PW];
 
   const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
   for (int e = tid; e < M1 * N1; e += blockDim.x) sD1[e] = a.D1[e];
@@ -115,7 +117,7 @@ __global__ void __launch_bounds__(kWave* kWaveWaves)
   auto g1 = [&](int i, int ik) { return sG1P[ik * N1 + (i % LR) * NRI + i / LR]; };
   auto g2 = [&](int jk, int j) { return sG2P[jk * N2 + (j % C::LC) * NCJ + j / C::LC]; };
 
-  for (int64_t k = (int64_t)blockIdx.x * kWaveWaves + wv; k < a.N; k += (int64_t)gridDim.x * kWaveWaves) {
+  for (int64_t k = (int64_t)blockIdx.x * C::WPB + wv; k < a.N; k += (int64_t)gridDim.x * C::WPB) {
     T yy = 0;
     for (int e = lane; e < M; e += kWave) {
       const T v = a.Yh ? (T)bf16_to_float(a.Yh[k * M + e]) : a.Y[k * M + e];
@@ -314,11 +316,35 @@ __global__ void __launch_bounds__(kWave* kWaveWaves)
   }
 }
 
+// Resident workgroups of a kernel on the current device (CUs x workgroups per CU), cached
+// per device; 0 when the query fails.
+template <typename T, class C>
+int64_t resident_blocks() {
+  constexpr int kMaxDev = 16;
+  static int64_t cache[kMaxDev] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < kMaxDev && cache[dev] > 0) return cache[dev];
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&omp_wave_kernel<T, C>),
+                                                   kWave * C::WPB, 0) != hipSuccess)
+    return 0;
+  const int64_t r = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+  if (dev < kMaxDev) cache[dev] = r;
+  return r;
+}
+
+// Persistent launch: as many workgroups as fit on the device at once, each wave looping
+// over signals, so the dictionary tables are staged once per resident workgroup and a
+// wave starts its next signal as soon as it finishes one.
 template <typename T, class C>
 hipError_t launch_wcfg(const OmpArgs<T>& a, hipStream_t st) {
-  int64_t blocks = (a.N + kWaveWaves - 1) / kWaveWaves;
+  int64_t blocks = (a.N + C::WPB - 1) / C::WPB;
+  const int64_t resident = resident_blocks<T, C>();
+  if (resident > 0 && blocks > resident) blocks = resident;
   if (blocks > kWaveMaxBlocks) blocks = kWaveMaxBlocks;
-  hipLaunchKernelGGL((omp_wave_kernel<T, C>), dim3((unsigned)blocks), dim3(kWave * kWaveWaves), 0, st, a);
+  hipLaunchKernelGGL((omp_wave_kernel<T, C>), dim3((unsigned)blocks), dim3(kWave * C::WPB), 0, st, a);
   return hipGetLastError();
 }
 
@@ -328,14 +354,16 @@ struct WaveVariant {
   hipError_t (*f64)(const OmpArgs<double>&, hipStream_t);
 };
 
-// Shapes with a one-wave-per-signal register kernel: (m1, m2, n1, n2, s, lane grid LR x LC)
-#define SDL_WAVE_SHAPES(X)                                                                      \
-  X(12, 12, 20, 20, 10, 4, 10) X(12, 12, 24, 24, 12, 8, 8) X(16, 16, 32, 32, 16, 8, 8)           \
-  X(32, 24, 48, 36, 20, 16, 4)
+// Shapes with a one-wave-per-signal register kernel:
+// (m1, m2, n1, n2, s, lane grid LR x LC, waves per workgroup)
+#define SDL_WAVE_SHAPES(X)                                                                            \
+  X(12, 12, 20, 20, 10, 4, 10, 4) X(12, 12, 24, 24, 12, 8, 8, 4) X(16, 16, 32, 32, 16, 8, 8, 4)        \
+  X(32, 24, 48, 36, 20, 16, 4, 4)
 
 const WaveVariant kWaveVariants[] = {
-#define X(A_, B_, C_, D_, E_, F_, G_) \
-  {A_, B_, C_, D_, E_, F_, G_, &launch_wcfg<float, WCfg<A_, B_, C_, D_, E_, F_, G_>>, &launch_wcfg<double, WCfg<A_, B_, C_, D_, E_, F_, G_>>},
+#define X(A_, B_, C_, D_, E_, F_, G_, H_)                       \
+  {A_, B_, C_, D_, E_, F_, G_, &launch_wcfg<float, WCfg<A_, B_, C_, D_, E_, F_, G_, H_>>, \
+   &launch_wcfg<double, WCfg<A_, B_, C_, D_, E_, F_, G_, H_>>},
     SDL_WAVE_SHAPES(X)
 #undef X
 };
