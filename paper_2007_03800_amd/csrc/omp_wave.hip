@@ -316,33 +316,11 @@ __global__ void __launch_bounds__(kWave* C::WPB)
   }
 }
 
-// Resident workgroups of a kernel on the current device (CUs x workgroups per CU), cached
-// per device; 0 when the query fails.
-template <typename T, class C>
-int64_t resident_blocks() {
-  constexpr int kMaxDev = 16;
-  static int64_t cache[kMaxDev] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
-  if (dev < kMaxDev && cache[dev] > 0) return cache[dev];
-  int cus = 0, per_cu = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&omp_wave_kernel<T, C>),
-                                                   kWave * C::WPB, 0) != hipSuccess)
-    return 0;
-  const int64_t r = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
-  if (dev < kMaxDev) cache[dev] = r;
-  return r;
-}
-
-// Persistent launch: as many workgroups as fit on the device at once, each wave looping
-// over signals, so the dictionary tables are staged once per resident workgroup and a
-// wave starts its next signal as soon as it finishes one.
+// One signal per wave up to kWaveMaxBlocks workgroups (a persistent grid measured slower:
+// static striding leaves waves idle at the end).
 template <typename T, class C>
 hipError_t launch_wcfg(const OmpArgs<T>& a, hipStream_t st) {
   int64_t blocks = (a.N + C::WPB - 1) / C::WPB;
-  const int64_t resident = resident_blocks<T, C>();
-  if (resident > 0 && blocks > resident) blocks = resident;
   if (blocks > kWaveMaxBlocks) blocks = kWaveMaxBlocks;
   hipLaunchKernelGGL((omp_wave_kernel<T, C>), dim3((unsigned)blocks), dim3(kWave * C::WPB), 0, st, a);
   return hipGetLastError();
