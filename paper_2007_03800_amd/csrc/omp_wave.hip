@@ -33,12 +33,16 @@ namespace {
 
 constexpr int kWaveMaxBlocks = 4096;
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // WPB_: signals (waves) per workgroup, chosen per shape so that the dictionary tables
 // shared by a workgroup plus its waves' buffers leave room for as many waves per CU as
 // the registers allow
-template <int M1_, int M2_, int N1_, int N2_, int S_, int LR_, int LC_, int WPB_>
+// MF_: FP32 on the matrix cores (omp_wave_mfma_kernel) instead of the vector ALUs
+template <int M1_, int M2_, int N1_, int N2_, int S_, int LR_, int LC_, int WPB_, bool MF_>
 struct WCfg {
   static constexpr int M1 = M1_, M2 = M2_, N1 = N1_, N2 = N2_, S = S_, LR = LR_, LC = LC_, WPB = WPB_;
+  static constexpr bool MF = MF_;
   static constexpr int LG = LR * LC, NRI = N1 / LR, NCJ = N2 / LC, E = NRI * NCJ;
   static constexpr int M = M1 * M2;
   static constexpr int NLI = S * (S + 1) / 2;   // packed rows of L^{-1} with the diagonal
@@ -77,6 +81,84 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Appends atom a = (ia, ja) with refreshed correlation bs to the support held by the wave
+// (lane k holds support element k: its atom my_i, my_j and coefficient my_x).  With the
+// Gram column g = G_{S,a}: w = L^{-1} g, v = L^{-T} w, delta^2 = G_aa - |w|^2 (again in FP64
+// below pivot_fp64 G_aa for FP32), c = bs / delta^2; then x_S -= c v, x_a = c, the new row
+// of L^{-1} is [-v^T, 1] / delta, and the refresh terms become gamma_q = c v_q (q < t),
+// gamma_t = -c.  Returns false, changing nothing, when delta^2 <= dep_eps G_aa (the atom
+// is numerically in the span of the support).  Ends with a wave sync: gam, supi, supj
+// and the new row are visible to the whole wave.
+template <typename T, class C, class G1f, class G2f>
+__device__ inline bool append_atom(int t, int lane, int ia, int ja, T bs, G1f g1, G2f g2, T* Li, T* gam, T* supi,
+                                   T* supj, T* xg, T* xw, T& my_x, int& my_i, int& my_j, const OmpArgs<T>& a) {
+  const T gaa = g1(ia, ia) * g2(ja, ja);
+  // w = L^{-1} g, lane k < t taking row k
+  if (lane < t) xg[lane] = g1(my_i, ia) * g2(ja, my_j);
+  wave_sync();
+  T w = 0;
+  if (lane < t) {
+    const T* row = Li + trow(lane);
+    T p0 = 0, p1 = 0;
+    int l = 0;
+    for (; l + 1 <= lane; l += 2) {
+      p0 += row[l] * xg[l];
+      p1 += row[l + 1] * xg[l + 1];
+    }
+    if (l <= lane) p0 += row[l] * xg[l];
+    w = p0 + p1;
+    xw[lane] = w;
+  }
+  wave_sync();
+  // |w|^2 in every lane, v = L^{-T} w in lane l < t (column l of L^{-1})
+  T ww = 0, v = 0;
+#pragma unroll 4
+  for (int k = 0; k < t; ++k) {
+    const T wk = xw[k];
+    ww += wk * wk;
+    if (lane <= k) v += Li[trow(k) + lane] * wk;
+  }
+  T d2 = gaa - ww;
+  if (sizeof(T) == 4 && d2 < (T)a.pivot_fp64 * gaa) {
+    // small pivot: w and |w|^2 again in FP64 (cancellation in G_aa - |w|^2)
+    double w64 = 0.0;
+    if (lane < t) {
+      const T* row = Li + trow(lane);
+      for (int l = 0; l <= lane; ++l)
+        w64 += (double)row[l] * ((double)g1((int)supi[l], ia) * (double)g2(ja, (int)supj[l]));
+    }
+    const double ww64 = wave_sum(lane < t ? w64 * w64 : 0.0);
+    wave_sync();
+    if (lane < t) xw[lane] = (T)w64;
+    wave_sync();
+    v = 0;
+    for (int k = 0; k < t; ++k)
+      if (lane <= k) v += Li[trow(k) + lane] * xw[k];
+    d2 = (T)((double)gaa - ww64);
+    if (lane == 0) atomicAdd(&a.counters[kCtrFp64Pivot], 1ull);
+  }
+  if (!(d2 > (T)a.dep_eps * gaa)) return false;
+  const T cst = bs / d2;
+  const T dinv = (T)1 / sqrt(d2);
+  T* rowt = Li + trow(t);
+  if (lane < t) {
+    rowt[lane] = -v * dinv;
+    my_x -= cst * v;
+    gam[lane] = cst * v;
+  }
+  if (lane == t) {
+    rowt[t] = dinv;
+    my_x = cst;
+    my_i = ia;
+    my_j = ja;
+    gam[t] = -cst;
+    supi[t] = (T)ia;
+    supj[t] = (T)ja;
+  }
+  wave_sync();
+  return true;
 }
 
 template <typename T, class C>
@@ -197,74 +279,11 @@ __global__ void __launch_bounds__(kWave* C::WPB)
         break;
       }
       const int ia = ba % N1, ja = ba / N1;
-      const T gaa = g1(ia, ia) * g2(ja, ja);
-      // w = L^{-1} g, lane k < t taking row k
-      if (lane < t) xg[lane] = g1(my_i, ia) * g2(ja, my_j);
-      wave_sync();
-      T w = 0;
-      if (lane < t) {
-        const T* row = Li + trow(lane);
-        T p0 = 0, p1 = 0;
-        int l = 0;
-        for (; l + 1 <= lane; l += 2) {
-          p0 += row[l] * xg[l];
-          p1 += row[l + 1] * xg[l + 1];
-        }
-        if (l <= lane) p0 += row[l] * xg[l];
-        w = p0 + p1;
-        xw[lane] = w;
-      }
-      wave_sync();
-      // |w|^2 in every lane, v = L^{-T} w in lane l < t (column l of L^{-1})
-      T ww = 0, v = 0;
-#pragma unroll 4
-      for (int k = 0; k < t; ++k) {
-        const T wk = xw[k];
-        ww += wk * wk;
-        if (lane <= k) v += Li[trow(k) + lane] * wk;
-      }
-      T d2 = gaa - ww;
-      if (sizeof(T) == 4 && d2 < (T)a.pivot_fp64 * gaa) {
-        // small pivot: w and |w|^2 again in FP64 (cancellation in G_aa - |w|^2)
-        double w64 = 0.0;
-        if (lane < t) {
-          const T* row = Li + trow(lane);
-          for (int l = 0; l <= lane; ++l)
-            w64 += (double)row[l] * ((double)g1((int)supi[l], ia) * (double)g2(ja, (int)supj[l]));
-        }
-        const double ww64 = wave_sum(lane < t ? w64 * w64 : 0.0);
-        wave_sync();
-        if (lane < t) xw[lane] = (T)w64;
-        wave_sync();
-        v = 0;
-        for (int k = 0; k < t; ++k)
-          if (lane <= k) v += Li[trow(k) + lane] * xw[k];
-        d2 = (T)((double)gaa - ww64);
-        if (lane == 0) atomicAdd(&a.counters[kCtrFp64Pivot], 1ull);
-      }
-      if (!(d2 > (T)a.dep_eps * gaa)) {
+      if (!append_atom<T, C>(t, lane, ia, ja, bs, g1, g2, Li, gam, supi, supj, xg, xw, my_x, my_i, my_j, a)) {
         early = true;
         break;
       }
-      const T cst = bs / d2;
-      const T dinv = (T)1 / sqrt(d2);
-      T* rowt = Li + trow(t);
-      if (lane < t) {
-        rowt[lane] = -v * dinv;
-        my_x -= cst * v;
-        gam[lane] = cst * v;
-      }
-      if (lane == t) {
-        rowt[t] = dinv;
-        my_x = cst;
-        my_i = ia;
-        my_j = ja;
-        gam[t] = -cst;
-        supi[t] = (T)ia;
-        supj[t] = (T)ja;
-      }
       if (act && sr == ia % LR && sc == ja % C::LC) used |= 1ull << ((ia / LR) * NCJ + ja / C::LC);
-      wave_sync();
       if (t + 1 < S && act) {
         // corr <- corr - cst (G_{:,a} - G_{:,S} v): terms gamma_q G1[:, i_q] G2[j_q, :],
         // four at a time (terms beyond t have gamma = 0 and atom 0)
@@ -316,13 +335,347 @@ __global__ void __launch_bounds__(kWave* C::WPB)
   }
 }
 
+// FP32 variant on the matrix cores.  The n1 x n2 correlations (padded to multiples of 16)
+// live in 16x16 tiles in the output layout of the 16x16x4 FP32 MFMA: register v of tile
+// (ti, tj) in lane l is C[16 ti + 4 (l / 16) + v, 16 tj + l % 16].  Four refresh terms are
+// one MFMA per tile: lane l supplies gamma_q G1[16 ti + l % 16, i_q] and G2[j_q, 16 tj + l % 16]
+// for q = q0 + l / 16, i.e. one LDS read per tile row and per tile column for four terms.
+// The first correlation runs the same way in two products, W = D1^T Y (k = m1) and
+// C = W D2 (k = m2).  Padding rows and columns are zero and never selected.
+// L^{-1} is kept in square storage twice, by rows and by columns (16-byte aligned, zero
+// outside the lower triangle of the rows written so far), so w = L^{-1} g, |w|^2 and
+// v = L^{-T} w are fixed-length float4 loops whose loads all issue at once.
+template <class C>
+struct MLay {
+  static constexpr int TR = (C::N1 + 15) / 16, TC = (C::N2 + 15) / 16, TQ = (C::M2 + 15) / 16;
+  static constexpr int P1 = 16 * TR, P2 = 16 * TC;
+  static constexpr int YQ = 16 * TQ + 1;  // Y^T staging stride (odd: conflict-free writes)
+  static constexpr int P1W = P1 + 1;      // W staging stride (odd: conflict-free writes)
+  static constexpr int SP = C::SP;        // multiple of 4
+  static constexpr int YT = (YQ * C::M1 + 3) / 4 * 4;
+  static constexpr int WSM = P1W * C::M2;
+  static constexpr int SCR = (2 * C::S + 5) * SP;  // L^{-1} by rows and by columns, gam, supi, supj, g, w
+  static constexpr int UNI = ((WSM > SCR ? WSM : SCR) + 3) / 4 * 4;  // W staging aliases the scratch
+  static constexpr int PW = YT + UNI;
+  static_assert(C::M1 % 4 == 0 && C::M2 % 4 == 0, "m1 and m2 are the k of the first-correlation MFMAs");
+  static_assert(TR * TC * 4 <= 64, "one mask bit per register element");
+};
+
+// append_atom for the square, zero-padded L^{-1} storage of the matrix-core kernel (same
+// arithmetic, same return and same visibility guarantee).
+template <class C, class G1f, class G2f>
+__device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs, G1f g1, G2f g2, float* LiR,
+                                      float* LiT, float* gam, float* supi, float* supj, float* xg, float* xw,
+                                      float& my_x, int& my_i, int& my_j, const OmpArgs<float>& a) {
+  constexpr int S = C::S, SP = C::SP, NC = SP / 4;
+  const float gaa = g1(ia, ia) * g2(ja, ja);
+  if (lane < t) xg[lane] = g1(my_i, ia) * g2(ja, my_j);
+  wave_sync();
+  // w = L^{-1} g in lane k < t (row k; entries past the diagonal and rows not yet
+  // written are zero, as are g and w past t)
+  const int rw = lane < S ? lane : S - 1;
+  const float4* row = reinterpret_cast<const float4*>(LiR + rw * SP);
+  const float4* g4 = reinterpret_cast<const float4*>(xg);
+  float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const float4 r = row[c], gg = g4[c];
+    p0 += r.x * gg.x;
+    p1 += r.y * gg.y;
+    p0 += r.z * gg.z;
+    p1 += r.w * gg.w;
+  }
+  if (lane < t) xw[lane] = p0 + p1;
+  wave_sync();
+  // |w|^2 in every lane, v = L^{-T} w in lane l < t (column l of L^{-1})
+  const float4* w4 = reinterpret_cast<const float4*>(xw);
+  const float4* col = reinterpret_cast<const float4*>(LiT + rw * SP);
+  float q0 = 0.f, q1 = 0.f, v0 = 0.f, v1 = 0.f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const float4 w = w4[c], cc = col[c];
+    q0 += w.x * w.x;
+    q1 += w.y * w.y;
+    q0 += w.z * w.z;
+    q1 += w.w * w.w;
+    v0 += cc.x * w.x;
+    v1 += cc.y * w.y;
+    v0 += cc.z * w.z;
+    v1 += cc.w * w.w;
+  }
+  float v = v0 + v1;
+  float d2 = gaa - (q0 + q1);
+  if (d2 < (float)a.pivot_fp64 * gaa) {
+    // small pivot: w and |w|^2 again in FP64 (cancellation in G_aa - |w|^2)
+    double w64 = 0.0;
+    if (lane < t)
+      for (int l = 0; l <= lane; ++l)
+        w64 += (double)LiR[lane * SP + l] * ((double)g1((int)supi[l], ia) * (double)g2(ja, (int)supj[l]));
+    const double ww64 = wave_sum(lane < t ? w64 * w64 : 0.0);
+    wave_sync();
+    if (lane < t) xw[lane] = (float)w64;
+    wave_sync();
+    v0 = 0.f;
+    v1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const float4 w = w4[c], cc = col[c];
+      v0 += cc.x * w.x;
+      v1 += cc.y * w.y;
+      v0 += cc.z * w.z;
+      v1 += cc.w * w.w;
+    }
+    v = v0 + v1;
+    d2 = (float)((double)gaa - ww64);
+    if (lane == 0) atomicAdd(&a.counters[kCtrFp64Pivot], 1ull);
+  }
+  if (!(d2 > (float)a.dep_eps * gaa)) return false;
+  const float cst = bs / d2;
+  const float dinv = 1.f / sqrtf(d2);
+  if (lane < t) {
+    LiR[t * SP + lane] = -v * dinv;
+    LiT[lane * SP + t] = -v * dinv;
+    my_x -= cst * v;
+    gam[lane] = cst * v;
+  }
+  if (lane == t) {
+    LiR[t * SP + t] = dinv;
+    LiT[t * SP + t] = dinv;
+    my_x = cst;
+    my_i = ia;
+    my_j = ja;
+    gam[t] = -cst;
+    supi[t] = (float)ia;
+    supj[t] = (float)ja;
+  }
+  wave_sync();
+  return true;
+}
+
+template <class C>
+__global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<float> a) {
+  using L = MLay<C>;
+  constexpr int M1 = C::M1, M2 = C::M2, N1 = C::N1, N2 = C::N2, S = C::S, M = C::M, SP = C::SP;
+  constexpr int TR = L::TR, TC = L::TC, TQ = L::TQ, P1 = L::P1, P2 = L::P2, YQ = L::YQ, P1W = L::P1W;
+  __shared__ __align__(16) float sD1T[P1 * M1];  // D1[p, i] at i + P1 p, zero for i >= n1
+  __shared__ __align__(16) float sD2T[P2 * M2];  // D2[q, j] at j + P2 q, zero for j >= n2
+  __shared__ __align__(16) float sG1P[P1 * N1];  // G1[i, ik] at i + P1 ik, zero for i >= n1
+  __shared__ __align__(16) float sG2P[P2 * N2];  // G2[jk, j] at j + P2 jk, zero for j >= n2
+  __shared__ __align__(16) float sW[C::WPB][L::PW];
+
+  const int tid = threadIdx.x, wv = tid / kWave, lane = tid % kWave;
+  const int r16 = lane % 16, k4 = lane / 16;
+  for (int e = tid; e < P1 * M1; e += blockDim.x) {
+    const int i = e % P1, p = e / P1;
+    sD1T[e] = i < N1 ? a.D1[p + M1 * i] : 0.f;
+  }
+  for (int e = tid; e < P2 * M2; e += blockDim.x) {
+    const int j = e % P2, q = e / P2;
+    sD2T[e] = j < N2 ? a.D2[q + M2 * j] : 0.f;
+  }
+  for (int e = tid; e < P1 * N1; e += blockDim.x) {
+    const int i = e % P1, ik = e / P1;
+    sG1P[e] = i < N1 ? a.G1[i + N1 * ik] : 0.f;
+  }
+  for (int e = tid; e < P2 * N2; e += blockDim.x) {
+    const int j = e % P2, jk = e / P2;
+    sG2P[e] = j < N2 ? a.G2[jk + N2 * j] : 0.f;
+  }
+  float* ysT = sW[wv];          // Y[p, q] at q + YQ p; columns m2 .. 16 TQ - 1 stay zero
+  float* Ws = ysT + L::YT;      // W[i, q] at i + P1W q (first correlation only)
+  float* LiR = Ws;              // L^{-1}[k, l] at k SP + l (greedy loop; aliases W)
+  float* LiT = LiR + S * SP;    // L^{-1}[k, l] at l SP + k
+  float* gam = LiT + S * SP;    // refresh coefficients gamma_q (zero beyond the support)
+  float* supi = gam + SP;       // support atoms i_q, j_q (exact small integers)
+  float* supj = supi + SP;
+  float* xg = supj + SP;        // exchange vectors: Gram column g, then w
+  float* xw = xg + SP;
+  if constexpr (16 * TQ > M2) {
+    for (int e = lane; e < (16 * TQ - M2) * M1; e += kWave) {
+      const int q = M2 + e % (16 * TQ - M2), p = e / (16 * TQ - M2);
+      ysT[q + YQ * p] = 0.f;
+    }
+  }
+  __syncthreads();
+  // G1 and G2 are symmetric: G1[i, ik] and G2[jk, j] from the padded tables
+  auto g1 = [&](int i, int ik) { return sG1P[i + P1 * ik]; };
+  auto g2 = [&](int jk, int j) { return sG2P[j + P2 * jk]; };
+  // register elements outside the n1 x n2 block: never selected
+  unsigned long long pad = 0ull;
+#pragma unroll
+  for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TC; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (16 * ti + 4 * k4 + v >= N1 || 16 * tj + r16 >= N2) pad |= 1ull << ((ti * TC + tj) * 4 + v);
+
+  for (int64_t k = (int64_t)blockIdx.x * C::WPB + wv; k < a.N; k += (int64_t)gridDim.x * C::WPB) {
+    float yy = 0.f;
+    for (int e = lane; e < M; e += kWave) {
+      const float v = a.Yh ? bf16_to_float(a.Yh[k * M + e]) : a.Y[k * M + e];
+      ysT[e / M1 + YQ * (e % M1)] = v;
+      yy += v * v;
+    }
+    const float ynorm = sqrtf(wave_sum(yy));
+    wave_sync();
+    {
+      // W = D1^T Y, rows padded with zeros to P1
+      f32x4 wt[TR][TQ];
+#pragma unroll
+      for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+        for (int tq = 0; tq < TQ; ++tq) wt[ti][tq] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int p0 = 0; p0 < M1; p0 += 4) {
+        const int p = p0 + k4;
+        float av[TR], bv[TQ];
+#pragma unroll
+        for (int ti = 0; ti < TR; ++ti) av[ti] = sD1T[16 * ti + r16 + P1 * p];
+#pragma unroll
+        for (int tq = 0; tq < TQ; ++tq) bv[tq] = ysT[16 * tq + r16 + YQ * p];
+#pragma unroll
+        for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+          for (int tq = 0; tq < TQ; ++tq)
+            wt[ti][tq] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti], bv[tq], wt[ti][tq], 0, 0, 0);
+      }
+#pragma unroll
+      for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+        for (int tq = 0; tq < TQ; ++tq) {
+          const int q = 16 * tq + r16;
+          if (q < M2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float wvv = wt[ti][tq][v];  // by value
+              Ws[16 * ti + 4 * k4 + v + P1W * q] = wvv;
+            }
+          }
+        }
+    }
+    wave_sync();
+    f32x4 acc[TR][TC];
+#pragma unroll
+    for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TC; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int q0 = 0; q0 < M2; q0 += 4) {
+      const int q = q0 + k4;
+      float av[TR], bv[TC];
+#pragma unroll
+      for (int ti = 0; ti < TR; ++ti) av[ti] = Ws[16 * ti + r16 + P1W * q];
+#pragma unroll
+      for (int tj = 0; tj < TC; ++tj) bv[tj] = sD2T[16 * tj + r16 + P2 * q];
+#pragma unroll
+      for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TC; ++tj) acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    }
+    wave_sync();  // W is read: the scratch it aliases is cleared next
+    for (int e = lane; e < L::SCR; e += kWave) LiR[e] = 0.f;
+    wave_sync();
+
+    unsigned long long used = pad;
+    float my_x = 0.f;
+    int my_i = 0, my_j = 0;
+    int t = 0;
+    bool early = false;
+    const float stop_thr = (float)a.stop_rel * ynorm;
+#pragma unroll 1
+    for (; t < S; ++t) {
+      // largest |corr| over the unselected atoms, ties to the smaller atom index; a lane's
+      // atoms in (tj, ti, v) order have increasing indices, so a strict comparison keeps
+      // the first of equal values.  Elements are read by value.
+      float bv = -1.f, bs = 0.f;
+      int ba = INT_MAX;
+#pragma unroll
+      for (int tj = 0; tj < TC; ++tj)
+#pragma unroll
+        for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int e = (ti * TC + tj) * 4 + v;
+            const float cv = acc[ti][tj][v];
+            const float av = fabsf(cv);
+            const bool take = !((used >> e) & 1ull) && av > bv;
+            bv = take ? av : bv;
+            bs = take ? cv : bs;
+            ba = take ? (16 * ti + 4 * k4 + v) + N1 * (16 * tj + r16) : ba;
+          }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const float ov = __shfl_xor(bv, o, kWave), os = __shfl_xor(bs, o, kWave);
+        const int oa = __shfl_xor(ba, o, kWave);
+        const bool take = ov > bv || (ov == bv && oa < ba);
+        bv = take ? ov : bv;
+        bs = take ? os : bs;
+        ba = take ? oa : ba;
+      }
+      if (ba == INT_MAX || !(bv > stop_thr)) {
+        early = true;
+        break;
+      }
+      const int ia = ba % N1, ja = ba / N1;
+      if (!append_atom_sq<C>(t, lane, ia, ja, bs, g1, g2, LiR, LiT, gam, supi, supj, xg, xw, my_x, my_i, my_j, a)) {
+        early = true;
+        break;
+      }
+      if (r16 == ja % 16 && k4 == (ia % 16) / 4) used |= 1ull << (((ia / 16) * TC + ja / 16) * 4 + ia % 4);
+      if (t + 1 < S) {
+        // corr <- corr - cst (G_{:,a} - G_{:,S} v), four terms gamma_q G1[:, i_q] G2[j_q, :]
+        // per MFMA (terms beyond t have gamma = 0 and atom 0)
+#pragma unroll 1
+        for (int q0 = 0; q0 <= t; q0 += 4) {
+          const int q = q0 + k4;
+          const float gq = gam[q];
+          const int iq = (int)supi[q], jq = (int)supj[q];
+          float av[TR], bv2[TC];
+#pragma unroll
+          for (int ti = 0; ti < TR; ++ti) av[ti] = gq * sG1P[16 * ti + r16 + P1 * iq];
+#pragma unroll
+          for (int tj = 0; tj < TC; ++tj) bv2[tj] = sG2P[16 * tj + r16 + P2 * jq];
+#pragma unroll
+          for (int ti = 0; ti < TR; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < TC; ++tj)
+              acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti], bv2[tj], acc[ti][tj], 0, 0, 0);
+        }
+      }
+    }
+    // explicit residual Y - sum_q x_q d1_{i_q} d2_{j_q}^T
+    float rr = 0.f;
+    for (int e = lane; e < M; e += kWave) {
+      const int p = e % M1, q = e / M1;
+      float r = ysT[q + YQ * p];
+      for (int u = 0; u < t; ++u)
+        r -= bcast(my_x, u) * sD1T[bcast(my_i, u) + P1 * p] * sD2T[bcast(my_j, u) + P2 * q];
+      rr += r * r;
+    }
+    rr = wave_sum(rr);
+    if (lane < S) {
+      a.supp[k * S + lane] = lane < t ? my_i + N1 * my_j : -1;
+      a.coef[k * S + lane] = lane < t ? my_x : 0.f;
+    }
+    if (lane == 0) {
+      if (a.res2) a.res2[k] = rr;
+      if (early) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+    }
+    wave_sync();
+  }
+}
+
 // One signal per wave up to kWaveMaxBlocks workgroups (a persistent grid measured slower:
 // static striding leaves waves idle at the end).
 template <typename T, class C>
 hipError_t launch_wcfg(const OmpArgs<T>& a, hipStream_t st) {
   int64_t blocks = (a.N + C::WPB - 1) / C::WPB;
   if (blocks > kWaveMaxBlocks) blocks = kWaveMaxBlocks;
-  hipLaunchKernelGGL((omp_wave_kernel<T, C>), dim3((unsigned)blocks), dim3(kWave * C::WPB), 0, st, a);
+  if constexpr (sizeof(T) == 4 && C::MF)
+    hipLaunchKernelGGL((omp_wave_mfma_kernel<C>), dim3((unsigned)blocks), dim3(kWave * C::WPB), 0, st, a);
+  else
+    hipLaunchKernelGGL((omp_wave_kernel<T, C>), dim3((unsigned)blocks), dim3(kWave * C::WPB), 0, st, a);
   return hipGetLastError();
 }
 
@@ -333,15 +686,15 @@ struct WaveVariant {
 };
 
 // Shapes with a one-wave-per-signal register kernel:
-// (m1, m2, n1, n2, s, lane grid LR x LC, waves per workgroup)
-#define SDL_WAVE_SHAPES(X)                                                                            \
-  X(12, 12, 20, 20, 10, 4, 10, 4) X(12, 12, 24, 24, 12, 8, 8, 4) X(16, 16, 32, 32, 16, 8, 8, 4)        \
-  X(32, 24, 48, 36, 20, 16, 4, 4)
+// (m1, m2, n1, n2, s, lane grid LR x LC, waves per workgroup, FP32 on the matrix cores)
+#define SDL_WAVE_SHAPES(X)                                                                       \
+  X(12, 12, 20, 20, 10, 4, 10, 4, true) X(12, 12, 24, 24, 12, 8, 8, 4, true)                    \
+  X(16, 16, 32, 32, 16, 8, 8, 4, true) X(32, 24, 48, 36, 20, 16, 4, 4, true)
 
 const WaveVariant kWaveVariants[] = {
-#define X(A_, B_, C_, D_, E_, F_, G_, H_)                       \
-  {A_, B_, C_, D_, E_, F_, G_, &launch_wcfg<float, WCfg<A_, B_, C_, D_, E_, F_, G_, H_>>, \
-   &launch_wcfg<double, WCfg<A_, B_, C_, D_, E_, F_, G_, H_>>},
+#define X(A_, B_, C_, D_, E_, F_, G_, H_, I_)                       \
+  {A_, B_, C_, D_, E_, F_, G_, &launch_wcfg<float, WCfg<A_, B_, C_, D_, E_, F_, G_, H_, I_>>, \
+   &launch_wcfg<double, WCfg<A_, B_, C_, D_, E_, F_, G_, H_, I_>>},
     SDL_WAVE_SHAPES(X)
 #undef X
 };
