@@ -335,6 +335,38 @@ __global__ void __launch_bounds__(kWave* C::WPB)
   }
 }
 
+// Largest (key, atom) pair of the wave, ties to the smaller atom; the result is uniform.
+// Keys are magnitudes as bit patterns (non-negative floats order like unsigned integers).
+// Within each row of 16 lanes: DPP quad swaps, half-row mirror and row mirror leave every
+// lane with its row's best; the four rows are then compared in scalar registers.
+template <int CTRL>
+__device__ inline void argmax_dpp_stage(unsigned& key, int& atom) {
+  const unsigned ok = (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, CTRL, 0xF, 0xF, false);
+  const int oa = __builtin_amdgcn_update_dpp(0, atom, CTRL, 0xF, 0xF, false);
+  const bool take = ok > key || (ok == key && oa < atom);
+  key = take ? ok : key;
+  atom = take ? oa : atom;
+}
+
+__device__ inline void wave_argmax_key(unsigned& key, int& atom) {
+  argmax_dpp_stage<0xB1>(key, atom);   // quad_perm [1,0,3,2]
+  argmax_dpp_stage<0x4E>(key, atom);   // quad_perm [2,3,0,1]
+  argmax_dpp_stage<0x141>(key, atom);  // row_half_mirror
+  argmax_dpp_stage<0x140>(key, atom);  // row_mirror
+  unsigned bk = (unsigned)__builtin_amdgcn_readlane((int)key, 0);
+  int ba = __builtin_amdgcn_readlane(atom, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const unsigned k = (unsigned)__builtin_amdgcn_readlane((int)key, 16 * r);
+    const int at = __builtin_amdgcn_readlane(atom, 16 * r);
+    const bool take = k > bk || (k == bk && at < ba);
+    bk = take ? k : bk;
+    ba = take ? at : ba;
+  }
+  key = bk;
+  atom = ba;
+}
+
 // FP32 variant on the matrix cores.  The n1 x n2 correlations (padded to multiples of 16)
 // live in 16x16 tiles in the output layout of the 16x16x4 FP32 MFMA: register v of tile
 // (ti, tj) in lane l is C[16 ti + 4 (l / 16) + v, 16 tj + l % 16].  Four refresh terms are
@@ -588,7 +620,8 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
       // largest |corr| over the unselected atoms, ties to the smaller atom index; a lane's
       // atoms in (tj, ti, v) order have increasing indices, so a strict comparison keeps
       // the first of equal values.  Elements are read by value.
-      float bv = -1.f, bs = 0.f;
+      unsigned bk = 0u;
+      float bs = 0.f;
       int ba = INT_MAX;
 #pragma unroll
       for (int tj = 0; tj < TC; ++tj)
@@ -598,26 +631,20 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
           for (int v = 0; v < 4; ++v) {
             const int e = (ti * TC + tj) * 4 + v;
             const float cv = acc[ti][tj][v];
-            const float av = fabsf(cv);
-            const bool take = !((used >> e) & 1ull) && av > bv;
-            bv = take ? av : bv;
+            const unsigned kv = __float_as_uint(cv) & 0x7FFFFFFFu;  // |cv|
+            const bool take = !((used >> e) & 1ull) && kv > bk;
+            bk = take ? kv : bk;
             bs = take ? cv : bs;
             ba = take ? (16 * ti + 4 * k4 + v) + N1 * (16 * tj + r16) : ba;
           }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const float ov = __shfl_xor(bv, o, kWave), os = __shfl_xor(bs, o, kWave);
-        const int oa = __shfl_xor(ba, o, kWave);
-        const bool take = ov > bv || (ov == bv && oa < ba);
-        bv = take ? ov : bv;
-        bs = take ? os : bs;
-        ba = take ? oa : ba;
-      }
-      if (ba == INT_MAX || !(bv > stop_thr)) {
+      wave_argmax_key(bk, ba);
+      if (ba == INT_MAX || !(__uint_as_float(bk) > stop_thr)) {
         early = true;
         break;
       }
       const int ia = ba % N1, ja = ba / N1;
+      // the signed correlation from the lane that holds the atom
+      bs = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, bs), 16 * ((ia % 16) / 4) + ja % 16));
       if (!append_atom_sq<C>(t, lane, ia, ja, bs, g1, g2, LiR, LiT, gam, supi, supj, xg, xw, my_x, my_i, my_j, a)) {
         early = true;
         break;
