@@ -175,7 +175,7 @@ def kernel_name(api, w):
     if t is None:
         return "generic (one wave per signal, all in LDS)"
     if t[3] == 2:
-        return "register-resident, one wave per signal, lanes %dx%d" % (t[0], t[1])
+        return "register-resident, one wave per signal, correlations in 16x16 MFMA tiles"
     return "register-resident lanes %dx%d, %d waves/SIMD%s" % (t[0], t[1], t[2], ", refresh on MFMA" if t[3] else "")
 
 

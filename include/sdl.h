@@ -155,7 +155,9 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
  * over atom rows (lanes_row) and columns (lanes_col), register budget in waves
  * per SIMD, the kind in matrix_core (0: multi-signal on the vector ALUs, 1: correlation
  * refresh on the matrix cores, 2: one wave per signal, whose dictionary sums run in
- * the standalone sums kernel), and the tuned time in ms (0 if not tuned; for kind 2
+ * the standalone sums kernel; in FP32 its correlations sit in 16x16 matrix-core tiles,
+ * lanes_row x lanes_col is the lane grid of the FP64 form), and the tuned time in ms
+ * (0 if not tuned; for kind 2
  * it includes the D1-side sums).  Returns 0 if the shape has a register-resident
  * kernel, SDL_E_UNSUPPORTED if it runs on the generic kernel.  The autotuner also times
  * kind 2 where it exists and keeps it if it beats the best fused variant. */
