@@ -55,6 +55,41 @@ def test_wave_fp32_matches_oracle(shape, rng):
     assert agree >= 0.97 * len(Y) and bad <= 1 and err <= 2e-4
 
 
+@pytest.mark.parametrize("shape", SHAPES, ids=ids)
+def test_wave_fp32_edges(shape, rng):
+    """One and five signals (fewer than a workgroup's waves), an exactly 1-sparse signal
+    (one atom, then the stop rule on a zero residual) and an all-zero signal."""
+    m1, m2, n1, n2, s, _ = shape
+    d1, d2 = rand_dicts(rng, m1, m2, n1, n2)
+    a = (7 * n1 + 3) % (n1 * n2)
+    for N in (1, 5):
+        Y, _ = planted(rng, N, d1, d2, s, noise=0.03)
+        if N == 5:
+            Y[1] = 2.5 * np.outer(d1[:, a % n1], d2[:, a // n1])
+            Y[2] = 0.0
+        so, co, _ = oracle.omp(Y, d1, d2, s)
+        sg, cg, rg = codes(Y, d1, d2, s, torch.float32)
+        agree, ties, bad, err = compare_codes(Y, d1, d2, sg, cg, so, co, 1e-4, 1e-4)
+        print(shape, N, "agree", agree, "ties", ties, "bad", bad, "err %.2e" % err)
+        assert bad == 0 and err <= 2e-4
+        if N == 5:
+            assert sg[1, 0] == a and np.all(sg[1, 1:] == -1) and np.all(so[1, 1:] == -1)
+            assert abs(cg[1, 0] - 2.5) < 1e-5 and rg[1] < 1e-8
+            assert np.all(sg[2] == -1) and np.all(cg[2] == 0) and rg[2] == 0
+
+
+def test_wave_bf16_signals_match_fp32_of_rounded(rng):
+    """BF16 signals are widened exactly on load: the codes equal, bit for bit, the FP32
+    codes of the rounded signals."""
+    m1, m2, n1, n2, s, N = 16, 16, 32, 32, 16, 64
+    d1, d2 = rand_dicts(rng, m1, m2, n1, n2)
+    Y, _ = planted(rng, N, d1, d2, s, noise=0.03)
+    Yb = torch.as_tensor(Y).to(torch.bfloat16)
+    sb, cb, rb = codes(Yb, d1, d2, s, torch.bfloat16)
+    sf, cf, rf = codes(Yb.double().numpy(), d1, d2, s, torch.float32)
+    assert np.array_equal(sb, sf) and np.array_equal(cb, cf) and np.array_equal(rb, rf)
+
+
 def test_wave_learn_tracks_oracle(rng):
     m1, m2, n1, n2, s, N = 32, 24, 48, 36, 20, 60
     t1, t2 = rand_dicts(rng, m1, m2, n1, n2)
