@@ -175,6 +175,8 @@ def kernel_name(api, w):
     if t is None:
         return "generic (one wave per signal, all in LDS)"
     if t[3] == 2:
+        if t[2] == 4:
+            return "register-resident, 16 lanes per signal on 4x4x1 MFMA quadrants, 4 signals per wave"
         return "register-resident, one wave per signal, correlations in 16x16 MFMA tiles"
     return "register-resident lanes %dx%d, %d waves/SIMD%s" % (t[0], t[1], t[2], ", refresh on MFMA" if t[3] else "")
 
@@ -195,11 +197,23 @@ def mixed_workload(api, oracle, synth):
     Ysub = Y[:nsub].double().cpu().numpy().transpose(0, 2, 1)  # the rounded signals, math layout
     s_o, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
     r_g = pr.res2[:nsub].double().cpu().numpy()
-    return {"workload": w.name, "N": w.N, "steps": w.iters, "dtype": "bf16 signals, f32 arithmetic, f64 solves",
-            "value": w.N * w.iters / dt, "unit": "signals/s per iteration", "ms_per_step": dt / w.iters * 1e3,
-            "rmse_first": float(trace[0][0]), "rmse_final": float(trace[0][-1]),
-            "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
-            **support_agreement(pr.supp[:nsub].cpu().numpy(), s_o), "omp_kernel": kernel_name(api, w)}
+    out = {"workload": w.name, "N": w.N, "steps": w.iters, "dtype": "bf16 signals, f32 arithmetic, f64 solves",
+           "value": w.N * w.iters / dt, "unit": "signals/s per iteration", "ms_per_step": dt / w.iters * 1e3,
+           "rmse_first": float(trace[0][0]), "rmse_final": float(trace[0][-1]),
+           "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
+           **support_agreement(pr.supp[:nsub].cpu().numpy(), s_o), "omp_kernel": kernel_name(api, w)}
+    # the same workload with FP32 signals (the plain path), for the ratio
+    del pr
+    Yf = device_signals(synth, w, torch.float32)
+
+    def fresh32():
+        return api.Problem(Yf, torch.from_numpy(e1.T.copy()).cuda(), torch.from_numpy(e2.T.copy()).cuda(), w.s)
+
+    _, trace32, dt32 = timed_learn(api, fresh32, w.iters)
+    out["fp32_value"] = w.N * w.iters / dt32
+    out["fp32_rmse_final"] = float(trace32[0][-1])
+    out["mixed_over_fp32"] = out["value"] / out["fp32_value"]
+    return out
 
 
 def uneven_workload(api, oracle, synth):

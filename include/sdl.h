@@ -102,8 +102,10 @@ typedef struct sdl_options {
   int32_t check_finite;     /* scan Y and dictionaries for NaN/Inf first (default 0) */
   int32_t timing;           /* fill stats->kernel_ms (eager launches with events; default 0) */
   int32_t kernel;           /* sparse-coding kernel: 0 auto, 1 generic, 2 register-resident multi-signal
-                               (FP32), 3 register-resident one wave per signal (large shapes); auto picks
-                               2, then 3, then 1, as compiled for the shape */
+                               (FP32), 3 register-resident with standalone sums (large shapes: one wave
+                               per signal, or in FP32 four signals per wave on matrix-core quadrants
+                               where compiled); auto picks 2, then 3, then 1, as compiled for the shape
+                               and as the autotuner measured */
   double stop_rel;          /* OMP stops when max |corr| <= stop_rel*||Y_k||_F; default 1e-14 (FP64), 1e-6 (FP32) */
   double dep_eps;           /* OMP stops when the new Gram pivot <= dep_eps*G_aa; default 1e-10 */
   double pivot_fp64;        /* FP32: pivots below pivot_fp64*G_aa are recomputed in FP64; default 1e-3 */
@@ -154,9 +156,11 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
 /* Kernel configuration currently used for an FP32 shape: lanes per signal split
  * over atom rows (lanes_row) and columns (lanes_col), register budget in waves
  * per SIMD, the kind in matrix_core (0: multi-signal on the vector ALUs, 1: correlation
- * refresh on the matrix cores, 2: one wave per signal, whose dictionary sums run in
- * the standalone sums kernel; in FP32 its correlations sit in 16x16 matrix-core tiles,
- * lanes_row x lanes_col is the lane grid of the FP64 form), and the tuned time in ms
+ * refresh on the matrix cores, 2: the standalone-sums path, whose dictionary sums run
+ * in the standalone sums kernel: one wave per signal (in FP32 on 16x16 matrix-core tiles;
+ * lanes_row x lanes_col is the lane grid of the FP64 form), or in FP32 at 12x12 signals
+ * with 20x20 or 24x24 atoms four signals per wave on 4x4x1 matrix-core quadrants; for
+ * kind 2 waves_per_simd reports the signals per wave, 1 or 4), and the tuned time in ms
  * (0 if not tuned; for kind 2
  * it includes the D1-side sums).  Returns 0 if the shape has a register-resident
  * kernel, SDL_E_UNSUPPORTED if it runs on the generic kernel.  The autotuner also times

@@ -749,10 +749,13 @@ hipError_t launch_omp_wave(const OmpArgs<T>& a, hipStream_t st) {
   const WaveVariant* v = find_wave(a.m1, a.m2, a.n1, a.n2, a.s);
   if (!v || a.index || a.sums_side) return hipErrorInvalidValue;
   if (a.N == 0) return hipSuccess;
-  if constexpr (sizeof(T) == 4)
+  if constexpr (sizeof(T) == 4) {
+    // FP32 shapes with a quadrant kernel run four signals per wave (omp_quad.hip)
+    if (omp_quad_supported(a.m1, a.m2, a.n1, a.n2, a.s)) return launch_omp_quad(a, st);
     return v->f32(a, st);
-  else
+  } else {
     return v->f64(a, st);
+  }
 }
 
 template hipError_t launch_omp_wave<float>(const OmpArgs<float>&, hipStream_t);

@@ -822,7 +822,8 @@ int sdl_tuned_config(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s, 
   double t = 0.0;
   const bool fast = omp_fast_supported<float>(m1, m2, n1, n2, s);
   if ((!fast || wave_chosen(m1, m2, n1, n2, s)) && omp_wave_grid(m1, m2, n1, n2, s, &lr, &lc)) {
-    mf = 2;  // one wave per signal
+    mf = 2;  // standalone-sums path: one wave per signal, or four on matrix-core quadrants
+    wpe = omp_quad_supported(m1, m2, n1, n2, s) ? 4 : 1;  // signals per wave
     t = wave_choice_ms(m1, m2, n1, n2, s);
   } else if (!tuned_config(m1, m2, n1, n2, s, &lr, &lc, &wpe, &mf, &t)) {
     return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for this shape");
@@ -845,7 +846,7 @@ int sdl_kernel_variants(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t 
   if (out && n < cap) {
     out[4 * n] = lr;
     out[4 * n + 1] = lc;
-    out[4 * n + 2] = 0;
+    out[4 * n + 2] = omp_quad_supported(m1, m2, n1, n2, s) ? 4 : 1;  // signals per wave
     out[4 * n + 3] = 2;
   }
   return n + 1;

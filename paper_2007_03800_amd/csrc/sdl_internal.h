@@ -89,6 +89,11 @@ void set_wave_choice(int m1, int m2, int n1, int n2, int s, bool on, double ms);
 double wave_choice_ms(int m1, int m2, int n1, int n2, int s);
 template <typename T>
 hipError_t launch_omp_wave(const OmpArgs<T>& a, hipStream_t st);
+// FP32 on matrix-core quadrants, 16 lanes and 4 signals per wave (omp_quad.hip): the FP32
+// form of the standalone-sums path for the shapes it is compiled for (launch_omp_wave
+// dispatches to it); no index mode, no sums epilogue.
+bool omp_quad_supported(int m1, int m2, int n1, int n2, int s);
+hipError_t launch_omp_quad(const OmpArgs<float>& a, hipStream_t st);
 // Matrix-core variants (omp_mfma.hip): four lanes per signal, refresh on 4x4x1 MFMA.
 struct MfmaVariant {
   int m1, m2, n1, n2, s, wpe;
