@@ -263,7 +263,7 @@ def main():
                          "the reference dispatch that scales hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the TMOD sums would be all-reduced across GPUs; see the design notes).", file=sys.stderr)
         sys.exit(2)
 

@@ -55,10 +55,10 @@ enum {
   SDL_E_NOMEM = -4,       /* workspace allocation failed */
   SDL_E_SINGULAR = -5,    /* update Gram sum not positive definite; dictionary kept */
   SDL_E_NONFINITE = -6,   /* check_finite found NaN/Inf in Y or a dictionary */
-  SDL_E_UNSUPPORTED = -7  /* valid but not supported by this build (see message) */
+  SDL_E_UNSUPPORTED = -7  /* valid but not supported by this library (see message) */
 };
 
-/* Limits of this build (per problem). */
+/* Limits of this library (per problem). */
 #define SDL_MAX_M 64      /* m1, m2 */
 #define SDL_MAX_N 64      /* n1, n2 */
 #define SDL_MAX_S 32      /* s */
