@@ -546,6 +546,7 @@ hipError_t omp_fast_init_device() {
   if (e == hipSuccess && n > 0) {
     g_num_cus = n;
     mfma_set_cus(n);
+    tmod_set_cus(n);
   }
   return e;
 }

@@ -227,7 +227,9 @@ void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Pla
     x.G2c = b.take<char>(elem * r.n2 * r.n2);
     const int na = r.n1 > r.n2 ? r.n1 : r.n2, mr = r.m1 > r.m2 ? r.m1 : r.m2;
     x.nent = na * na + mr * na;
-    const int nb1 = tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2), nb2 = tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1);
+    const size_t ae = elem == 8 ? 8 : 4;  // arithmetic element size (BF16 signals compute in FP32)
+    const int nb1 = tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2, r.s, r.n2, ae);
+    const int nb2 = tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1, r.s, r.n1, ae);
     x.nblk = nb1 > nb2 ? nb1 : nb2;
     const int rows = x.nblk > omp_fast_max_partial_rows() ? x.nblk : omp_fast_max_partial_rows();
     x.rblk = rmse_num_blocks(r.N);
@@ -385,7 +387,8 @@ TmodArgs<T> tmod_args(int side, const sdl_problem& r, const PBuf& b, const Plan&
 template <typename T>
 int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bool rescale, Launcher& L) {
   const TmodArgs<T> a = tmod_args<T>(side, r, b, pl);
-  const int nblk = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2) : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1);
+  const int nblk = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2, r.s, r.n2, sizeof(T))
+                              : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1, r.s, r.n1, sizeof(T));
   SDL_TRY(L.begin(1));
   HIP_TRY(launch_tmod_sums<T>(a, b.part, L.st));
   SDL_TRY(L.end());

@@ -124,7 +124,11 @@ size_t omp_generic_lds_bytes(int m1, int m2, int n1, int n2, int s, size_t elem)
 hipError_t omp_generic_init_device();
 
 // Workgroup partials of the standalone sums kernel (a fixed function of N and the shape).
-int tmod_num_blocks_for(int64_t N, int na, int mr, int mc);
+// workgroups (= partial rows) of the standalone sums kernel: na atoms being solved, mr
+// signal rows on that side, mc the other side's signal extent, s the sparsity, nbo the
+// other dictionary's atoms, elem the element size of the arithmetic
+int tmod_num_blocks_for(int64_t N, int na, int mr, int mc, int s, int nbo, size_t elem);
+void tmod_set_cus(int n);
 hipError_t tmod_sums_init_device();
 template <typename T>
 hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, hipStream_t st);

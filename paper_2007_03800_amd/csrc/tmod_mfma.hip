@@ -19,7 +19,7 @@ namespace sdl {
 namespace {
 
 constexpr int kWaves = 4;
-constexpr int kMaxBlocks = 512;
+constexpr int kMaxBlocksPerCu = 4;  // grid cap: one round of at most 4 workgroups per CU
 constexpr int kMaxDynLds = 160 * 1024;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -190,6 +190,39 @@ hipError_t launch_tp(int tr, const TmodArgs<T>& a, double* part, int nblk, int b
   }
 }
 
+// Workgroups of one instantiation that fit on a CU at once with `lds` bytes of LDS
+// (registers and LDS, as the runtime computes it); 1 if the query fails.
+template <typename T, int TP, int TR>
+int per_cu_tp_tr(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&tmod_sums_kernel<T, TP, TR>),
+                                                   kWave * kWaves, lds) != hipSuccess || n < 1)
+    n = 1;
+  return n;
+}
+
+template <typename T, int TP>
+int per_cu_tp(int tr, size_t lds) {
+  switch (tr) {
+    case 1: return per_cu_tp_tr<T, TP, 1>(lds);
+    case 2: return per_cu_tp_tr<T, TP, 2>(lds);
+    case 3: return per_cu_tp_tr<T, TP, 3>(lds);
+    default: return per_cu_tp_tr<T, TP, 4>(lds);
+  }
+}
+
+template <typename T>
+int per_cu(int tp, int tr, size_t lds) {
+  switch (tp) {
+    case 1: return per_cu_tp<T, 1>(tr, lds);
+    case 2: return per_cu_tp<T, 2>(tr, lds);
+    case 3: return per_cu_tp<T, 3>(tr, lds);
+    default: return per_cu_tp<T, 4>(tr, lds);
+  }
+}
+
+int g_tcus = 256;
+
 }  // namespace
 
 // batch size so one wave's staging stays near 12 KiB (FP32) / 24 KiB (FP64)
@@ -202,30 +235,46 @@ static int sums_batch(int na, int mr, int mc) {
   return bs;
 }
 
-int tmod_num_blocks_for(int64_t N, int na, int mr, int mc) {
+// dynamic LDS of one workgroup: four waves' staging plus the fixed dictionary (and at least
+// the end-of-kernel reduction buffer)
+static size_t sums_lds(int na, int mr, int mc, int s, int nbo, size_t elem) {
   const int bs = sums_batch(na, mr, mc);
+  const int tp = (na + 15) / 16, tr = (mr + 15) / 16;
+  const int K4 = (bs * mc + 3) & ~3;
+  size_t lds = ((size_t)kWaves * ((size_t)K4 * (16 * tp + 1 + 16 * tr + 1) + 2 * (size_t)bs * s) + (size_t)mc * nbo) * elem;
+  const size_t red = (size_t)kWaves * (na * na + mr * na) * elem;
+  return red > lds ? red : lds;
+}
+
+void tmod_set_cus(int n) {
+  if (n > 0) g_tcus = n;
+}
+
+// One round of resident workgroups (CUs x workgroups per CU, at most kMaxBlocksPerCu), or
+// fewer when the signals run out; the same count sizes the partial buffer and the
+// reduction.
+int tmod_num_blocks_for(int64_t N, int na, int mr, int mc, int s, int nbo, size_t elem) {
+  const int bs = sums_batch(na, mr, mc);
+  const int tp = (na + 15) / 16, tr = (mr + 15) / 16;
+  const size_t lds = sums_lds(na, mr, mc, s, nbo, elem);
+  int pc = elem == 8 ? per_cu<double>(tp, tr, lds) : per_cu<float>(tp, tr, lds);
+  if (pc > kMaxBlocksPerCu) pc = kMaxBlocksPerCu;
   int64_t b = (N + (int64_t)kWaves * bs - 1) / ((int64_t)kWaves * bs);
-  if (b > kMaxBlocks) b = kMaxBlocks;
+  if (b > (int64_t)g_tcus * pc) b = (int64_t)g_tcus * pc;
   if (b < 1) b = 1;
   return (int)b;
 }
-
-
 
 template <typename T>
 hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, hipStream_t st) {
   const int na = a.side == 1 ? a.n1 : a.n2;
   const int mr = a.side == 1 ? a.m1 : a.m2;
   const int mc = a.side == 1 ? a.m2 : a.m1;
+  const int nbo = a.side == 1 ? a.n2 : a.n1;
   const int bs = sums_batch(na, mr, mc);
-  const int nblk = tmod_num_blocks_for(a.N, na, mr, mc);
+  const int nblk = tmod_num_blocks_for(a.N, na, mr, mc, a.s, nbo, sizeof(T));
   const int tp = (na + 15) / 16, tr = (mr + 15) / 16;
-  const int K4 = (bs * mc + 3) & ~3;
-  const int mco = a.side == 1 ? a.n2 : a.n1;
-  size_t lds = ((size_t)kWaves * ((size_t)K4 * (16 * tp + 1 + 16 * tr + 1) + 2 * (size_t)bs * a.s) +
-                (size_t)mc * mco) * sizeof(T);
-  const size_t red = (size_t)kWaves * (na * na + mr * na) * sizeof(T);
-  if (red > lds) lds = red;
+  const size_t lds = sums_lds(na, mr, mc, a.s, nbo, sizeof(T));
   switch (tp) {
     case 1: return launch_tp<T, 1>(tr, a, part, nblk, bs, lds, st);
     case 2: return launch_tp<T, 2>(tr, a, part, nblk, bs, lds, st);
