@@ -532,15 +532,8 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
   // G1 and G2 are symmetric: G1[i, ik] and G2[jk, j] from the padded tables
   auto g1 = [&](int i, int ik) { return sG1P[i + P1 * ik]; };
   auto g2 = [&](int jk, int j) { return sG2P[j + P2 * jk]; };
-  // register elements outside the n1 x n2 block: never selected
-  unsigned long long pad = 0ull;
-#pragma unroll
-  for (int ti = 0; ti < TR; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < TC; ++tj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (16 * ti + 4 * k4 + v >= N1 || 16 * tj + r16 >= N2) pad |= 1ull << ((ti * TC + tj) * 4 + v);
+  // register elements outside the n1 x n2 block stay exactly zero (zero rows and columns
+  // in every table), so they are never selected
 
   for (int64_t k = (int64_t)blockIdx.x * C::WPB + wv; k < a.N; k += (int64_t)gridDim.x * C::WPB) {
     float yy = 0.f;
@@ -609,7 +602,6 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
     for (int e = lane; e < L::SCR; e += kWave) LiR[e] = 0.f;
     wave_sync();
 
-    unsigned long long used = pad;
     float my_x = 0.f;
     int my_i = 0, my_j = 0;
     int t = 0;
@@ -629,10 +621,9 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
         for (int ti = 0; ti < TR; ++ti)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int e = (ti * TC + tj) * 4 + v;
             const float cv = acc[ti][tj][v];
             const unsigned kv = __float_as_uint(cv) & 0x7FFFFFFFu;  // |cv|
-            const bool take = !((used >> e) & 1ull) && kv > bk;
+            const bool take = kv > bk;
             bk = take ? kv : bk;
             bs = take ? cv : bs;
             ba = take ? (16 * ti + 4 * k4 + v) + N1 * (16 * tj + r16) : ba;
@@ -643,13 +634,18 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
         break;
       }
       const int ia = ba % N1, ja = ba / N1;
+      // no explicit masking: a chosen atom's correlation is zero up to rounding after the
+      // re-fit, so picking it again means every correlation is at rounding level: stop
+      if (__ballot(lane < t && my_i == ia && my_j == ja) != 0ull) {
+        early = true;
+        break;
+      }
       // the signed correlation from the lane that holds the atom
       bs = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, bs), 16 * ((ia % 16) / 4) + ja % 16));
       if (!append_atom_sq<C>(t, lane, ia, ja, bs, g1, g2, LiR, LiT, gam, supi, supj, xg, xw, my_x, my_i, my_j, a)) {
         early = true;
         break;
       }
-      if (r16 == ja % 16 && k4 == (ia % 16) / 4) used |= 1ull << (((ia / 16) * TC + ja / 16) * 4 + ia % 4);
       if (t + 1 < S) {
         // corr <- corr - cst (G_{:,a} - G_{:,S} v), four terms gamma_q G1[:, i_q] G2[j_q, :]
         // per MFMA (terms beyond t have gamma = 0 and atom 0)
