@@ -20,11 +20,12 @@ from tests.conftest import planted, rand_dicts
 pytestmark = pytest.mark.gpu
 
 # (shape, dtype, kernel option): the matrix-core kernel (auto at this shape), a VALU
-# multi-signal shape, the one-wave kernel (FP32 on matrix-core tiles: exact, padded in
-# both dimensions, padded in one; FP64 on the vector ALUs), the generic kernel in both
-# precisions
+# multi-signal shape, the standalone-sums kernels (FP32 one-wave on matrix-core tiles:
+# exact and padded in one dimension; FP32 quadrants: padded and exact; FP64 one-wave on
+# the vector ALUs), the generic kernel in both precisions
 KERNELS = [((8, 8, 16, 16, 8), torch.float32, 0), ((12, 12, 20, 20, 10), torch.float32, 2),
            ((16, 16, 32, 32, 16), torch.float32, 3), ((12, 12, 20, 20, 10), torch.float32, 3),
+           ((12, 12, 24, 24, 12), torch.float32, 3),
            ((32, 24, 48, 36, 20), torch.float32, 3), ((5, 9, 11, 6, 7), torch.float32, 1),
            ((8, 8, 12, 12, 4), torch.float64, 1), ((32, 24, 48, 36, 20), torch.float64, 3)]
 ids = ["x".join(map(str, k[0])) + "-" + ("f32" if k[1] == torch.float32 else "f64") + "-k%d" % k[2] for k in KERNELS]

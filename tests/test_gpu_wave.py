@@ -102,6 +102,15 @@ def test_wave_learn_tracks_oracle(rng):
     np.testing.assert_allclose(pr.d1(), ref["D1"], atol=1e-9)
 
 
+def test_standalone_sums_path_reports_signals_per_wave():
+    """Kernel option 3 in FP32: 16 lanes and four signals per wave on matrix-core quadrants at
+    12x12 signals with 20x20 or 24x24 atoms, one wave per signal at the larger shapes."""
+    for shape, spw in (((12, 12, 24, 24, 12), 4), ((12, 12, 20, 20, 10), 4), ((16, 16, 32, 32, 16), 1),
+                       ((32, 24, 48, 36, 20), 1)):
+        kinds = [v for v in api.kernel_variants(*shape) if v[3] == 2]
+        assert len(kinds) == 1 and kinds[0][2] == spw, (shape, kinds)
+
+
 def test_wave_unsupported_shape_rejected(rng):
     d1, d2 = rand_dicts(rng, 8, 8, 12, 12)
     pr = api.Problem.from_math(rng.standard_normal((10, 8, 8)), d1, d2, 4)
