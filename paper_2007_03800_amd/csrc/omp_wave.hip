@@ -5,10 +5,11 @@
 // correlations do not fit the multi-signal layouts of omp_fast.hip / omp_mfma.hip
 // (hundreds to ~2000 atoms, s up to 32):
 //
-//  * Lane (sr, sc) of an LR x LC grid (LR*LC <= 64) holds the correlations of atoms
-//    i = sr + LR*ri, j = sc + LC*cj in E = (n1/LR)(n2/LC) registers, so each Gram-form
-//    refresh term gamma_k G1[:, i_k] G2[j_k, :] is an E-element rank-one update from
-//    NRI + NCJ contiguous LDS reads.
+//  * FP64 (omp_wave_kernel): lane (sr, sc) of an LR x LC grid (LR*LC <= 64) holds the
+//    correlations of atoms i = sr + LR*ri, j = sc + LC*cj in E = (n1/LR)(n2/LC) registers,
+//    so each Gram-form refresh term gamma_k G1[:, i_k] G2[j_k, :] is an E-element rank-one
+//    update from NRI + NCJ contiguous LDS reads.  FP32 (omp_wave_mfma_kernel): the
+//    correlations sit in 16x16 tiles of the 16x16x4 MFMA result layout (see that kernel).
 //  * The least squares is carried by the inverse of the Cholesky factor, L^{-1}, kept
 //    in LDS (packed rows with the diagonal).  Appending atom a with Gram column g = G_{S,a}
 //    needs w = L^{-1} g (the new row of L), v = L^{-T} w and delta^2 = G_aa - |w|^2; the
@@ -19,11 +20,12 @@
 //    refresh reads them four terms at a time (padding terms have gamma = 0), so their
 //    LDS latencies overlap.
 //  * Loops over the greedy step and the support are runtime loops: code size does not
-//    grow with s.  Chosen atoms are masked explicitly (one bit per register element),
-//    as in the generic kernel and the FP64 reference.
+//    grow with s.  In FP64 chosen atoms are masked explicitly (one bit per register
+//    element), as in the generic kernel and the FP64 reference; in FP32 a repeated pick
+//    stops the signal, as in the other FP32 kernels.
 //  * FP32 pivots below pivot_fp64 * G_aa are recomputed in FP64.
 // No TMOD sums epilogue: with this kernel the dictionary updates use the standalone
-// sums kernel.
+// sums kernel.  FP32 shapes compiled in omp_quad.hip are dispatched there instead.
 #include <limits.h>
 
 #include "sdl_internal.h"
