@@ -16,8 +16,10 @@
 //    order), then across the signal's 16 lanes (one DPP row) by quad swaps, half-row
 //    mirror and row mirror on (magnitude, atom) pairs, ties to the smaller atom.
 //  * The chosen atom's correlation is recomputed exactly (d1_i^T Y d2_j minus the
-//    support's contribution), the Cholesky factor lives in LDS, and the greedy step is
-//    branch-free (results committed with selects), as in omp_mfma.hip.
+//    support's contribution) and the greedy step is branch-free (results committed with
+//    selects), as in omp_mfma.hip.  The least squares carries the inverse Cholesky factor
+//    (in LDS), so both triangular products of a step are independent dot products: with
+//    only four signals per wave, substitution chains would leave the SIMD idle.
 //  * No sums epilogue: dictionary updates use the standalone sums kernel.
 #include <limits.h>
 
@@ -197,14 +199,13 @@ __global__ void __launch_bounds__(kWave* kQWaves) __attribute__((amdgpu_waves_pe
 
     // ---- greedy loop
     float* L = sL[wv] + g * C::NLP;
-    float dinv[S], x[S];
+    float x[S];
     int ia[S], ja[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
       x[k] = 0.f;
       ia[k] = 0;
       ja[k] = 0;
-      dinv[k] = 0.f;
     }
     bool active = valid;
     int nsel = 0;
@@ -253,34 +254,37 @@ __global__ void __launch_bounds__(kWave* kQWaves) __attribute__((amdgpu_waves_pe
       if (stop) active = false;
       // The step runs in every lane (a stopped signal computes values it never commits):
       // results are committed with selects below.
-      float w[S > 1 ? S - 1 : 1];
+      // L^{-1} (rows with the diagonal, in LDS) instead of L: with g = G_{S,a}, w = L^{-1} g
+      // and v = L^{-T} w are independent dot products, delta^2 = G_aa - |w|^2, and the new
+      // row of L^{-1} is [-v^T, 1] / delta
+      float w[S > 1 ? S - 1 : 1], gv[S > 1 ? S - 1 : 1];
       const float gaa = sG1[it + NP1 * it] * sG2[jt + NP2 * jt];
       float d2;
       {
+#pragma unroll
+        for (int k = 0; k < t; ++k) gv[k] = sG1[ia[k] + NP1 * it] * sG2[ja[k] + NP2 * jt];
         float ww = 0.f;
 #pragma unroll
         for (int k = 0; k < t; ++k) {
-          float b = sG1[ia[k] + NP1 * it] * sG2[ja[k] + NP2 * jt];
+          float b = 0.f;
 #pragma unroll
-          for (int l = 0; l < k; ++l) b -= L[tri(k, l)] * w[l];
-          w[k] = b * dinv[k];
-          ww += w[k] * w[k];
+          for (int l = 0; l <= k; ++l) b += L[tri(k, l)] * gv[l];
+          w[k] = b;
+          ww += b * b;
         }
         d2 = gaa - ww;
         if (active && d2 < piv * gaa) {
-          // small pivot: the row again in FP64 (cancellation in G_aa - |w|^2)
-          double w64[S > 1 ? S - 1 : 1];
+          // small pivot: w and |w|^2 again in FP64 (cancellation in G_aa - |w|^2)
           double accd = 0.0;
 #pragma unroll
           for (int k = 0; k < t; ++k) {
-            double b = (double)sG1[ia[k] + NP1 * it] * (double)sG2[ja[k] + NP2 * jt];
+            double b = 0.0;
 #pragma unroll
-            for (int l = 0; l < k; ++l) b -= (double)L[tri(k, l)] * w64[l];
-            w64[k] = b * (double)dinv[k];
-            accd += w64[k] * w64[k];
+            for (int l = 0; l <= k; ++l)
+              b += (double)L[tri(k, l)] * ((double)sG1[ia[l] + NP1 * it] * (double)sG2[ja[l] + NP2 * jt]);
+            w[k] = (float)b;
+            accd += b * b;
           }
-#pragma unroll
-          for (int k = 0; k < t; ++k) w[k] = (float)w64[k];
           d2 = (float)((double)gaa - accd);
           if (cs == 0) atomicAdd(&a.counters[kCtrFp64Pivot], 1ull);
         }
@@ -299,25 +303,26 @@ __global__ void __launch_bounds__(kWave* kQWaves) __attribute__((amdgpu_waves_pe
         }
         cor = row_sum(part);
 #pragma unroll
-        for (int k = 0; k < t; ++k) cor -= sG1[ia[k] + NP1 * it] * sG2[ja[k] + NP2 * jt] * x[k];
+        for (int k = 0; k < t; ++k) cor -= gv[k] * x[k];
       }
       {
         float vv[S > 1 ? S - 1 : 1];
 #pragma unroll
-        for (int k = t - 1; k >= 0; --k) {
-          float b = w[k];
+        for (int l = 0; l < t; ++l) {
+          float b = 0.f;
 #pragma unroll
-          for (int l = k + 1; l < t; ++l) b -= L[tri(l, k)] * vv[l];
-          vv[k] = b * dinv[k];
+          for (int k = l; k < t; ++k) b += L[tri(k, l)] * w[k];
+          vv[l] = b;
         }
         const float cst = cor / d2;
+        const float dinv = rsqrtf(d2);
         // the signal's lanes write the same row: no divergent store
 #pragma unroll
         for (int k = 0; k < t; ++k) {
-          L[tri(t, k)] = w[k];
+          L[tri(t, k)] = -vv[k] * dinv;
           x[k] = active ? x[k] - cst * vv[k] : x[k];
         }
-        dinv[t] = rsqrtf(d2);
+        L[tri(t, t)] = dinv;
         x[t] = active ? cst : 0.f;
         ia[t] = active ? it : 0;
         ja[t] = active ? jt : 0;
