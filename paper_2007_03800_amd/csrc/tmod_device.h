@@ -26,7 +26,7 @@ __device__ void write_copies(const double* D, int mr, int na, T* Dc, double* G64
 // (na rows of na + mr entries, padded), the new dictionary, the pivots' reference
 // diagonal and the used-atom list.
 __host__ __device__ inline size_t solve_lds_bytes(int na, int mr) {
-  return sizeof(double) * ((size_t)na * (na + mr + 1) + (size_t)mr * na + na) + sizeof(int) * (na + 1) + 16;
+  return sizeof(double) * ((size_t)na * (na + mr + 1) + (size_t)(mr + 1) * na + na) + sizeof(int) * (na + 1) + 16;
 }
 
 // Whole workgroup (tid = 0..nt-1).  sums = [A (na x na) | B (mr x na)], column-major,
@@ -49,8 +49,9 @@ __device__ void solve_update_block(const double* sums, int mr, int na, double* D
                                    int tid, int nt) {
   const int ldm = na + mr + 1;
   double* M = reinterpret_cast<double*>(smem);  // M[k * ldm + c], c < nu: A_UU, c >= nu: B_U^T
-  double* Dn = M + (size_t)na * ldm;             // new dictionary, mr x na column-major
-  double* diag0 = Dn + (size_t)mr * na;
+  const int ldd = mr + 1;                        // odd column stride: Gram reads spread over banks
+  double* Dn = M + (size_t)na * ldm;             // new dictionary, mr x na column-major, stride ldd
+  double* diag0 = Dn + (size_t)ldd * na;
   int* U = reinterpret_cast<int*>(diag0 + na);
   int* nu_s = U + na;
   const double* A = sums;
@@ -65,7 +66,7 @@ __device__ void solve_update_block(const double* sums, int mr, int na, double* D
       if (nu < na) atomicAdd(&counters[kCtrUnusedAtoms], (unsigned long long)(na - nu));
     }
   }
-  for (int e = tid; e < mr * na; e += nt) Dn[e] = D[e];
+  for (int e = tid; e < mr * na; e += nt) Dn[e % mr + ldd * (e / mr)] = D[e];
   for (int i = tid; i < na; i += nt) w[i] = 1.0;
   __syncthreads();
   const int nu = *nu_s, ncol = nu + mr;
@@ -103,7 +104,7 @@ __device__ void solve_update_block(const double* sums, int mr, int na, double* D
       if (nrm > 0.0) {
         const int i = U[k];
         w[i] = nrm;
-        for (int p = 0; p < mr; ++p) Dn[p + mr * i] = (M[k * ldm + nu + p] * inv) / nrm;
+        for (int p = 0; p < mr; ++p) Dn[p + ldd * i] = (M[k * ldm + nu + p] * inv) / nrm;
       }
     }
   } else if (tid == 0) {
@@ -112,13 +113,14 @@ __device__ void solve_update_block(const double* sums, int mr, int na, double* D
   }
   __syncthreads();
   for (int e = tid; e < mr * na; e += nt) {
-    D[e] = Dn[e];
-    Dc[e] = (T)Dn[e];
+    const double v = Dn[e % mr + ldd * (e / mr)];
+    D[e] = v;
+    Dc[e] = (T)v;
   }
   for (int e = tid; e < na * na; e += nt) {
     const int i = e % na, j = e / na;
     double v = 0.0;
-    for (int p = 0; p < mr; ++p) v += Dn[p + mr * i] * Dn[p + mr * j];
+    for (int p = 0; p < mr; ++p) v += Dn[p + ldd * i] * Dn[p + ldd * j];
     G64[e] = v;
     Gc[e] = (T)v;
   }
