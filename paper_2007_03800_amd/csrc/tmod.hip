@@ -65,9 +65,26 @@ __global__ void __launch_bounds__(kSolveThreads)
   solve_update_block<T>(sums, mr, na, D, Dc, G64, Gc, w, status, counters, smem_raw, tid, blockDim.x);
 }
 
+// The dictionary's copies and Gram matrix (as write_copies), with D staged in LDS at an odd
+// column stride first: the Gram entries then read LDS without bank conflicts instead of
+// global memory.
 template <typename T>
 __global__ void dict_prep_kernel(const double* D, int mr, int na, T* Dc, double* G64, T* Gc) {
-  write_copies<T>(D, mr, na, Dc, G64, Gc, threadIdx.x, blockDim.x);
+  __shared__ double sD[(SDL_MAX_M + 1) * SDL_MAX_N];
+  const int ldd = mr + 1, tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < mr * na; e += nt) {
+    const double v = D[e];
+    sD[e % mr + ldd * (e / mr)] = v;
+    Dc[e] = (T)v;
+  }
+  __syncthreads();
+  for (int e = tid; e < na * na; e += nt) {
+    const int i = e % na, j = e / na;
+    double v = 0.0;
+    for (int p = 0; p < mr; ++p) v += sD[p + ldd * i] * sD[p + ldd * j];
+    G64[e] = v;
+    Gc[e] = (T)v;
+  }
 }
 
 template <typename T>

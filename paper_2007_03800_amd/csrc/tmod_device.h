@@ -1,6 +1,6 @@
-// Device routines of the TMOD dictionary update shared by several kernels:
-// the FP64 solve on the used atoms with normalisation (Corollary 1 / Proposition 1)
-// and the refresh of the compute-type dictionary copy and Gram matrix.
+// Device routine of the TMOD dictionary update: the FP64 solve on the used atoms with
+// normalisation (Corollary 1 / Proposition 1), which also rewrites the compute-type
+// dictionary copy and the Gram matrix.
 #pragma once
 
 #include "sdl_internal.h"
@@ -8,19 +8,6 @@
 namespace sdl {
 
 constexpr double kSpdRelTol = 1e-12;  // Cholesky pivot <= tol * diagonal entry -> not positive definite
-
-// D (mr x na FP64) -> compute-type copy, FP64 and compute-type Gram D^T D; threads t0..t0+nt-1.
-template <typename T>
-__device__ void write_copies(const double* D, int mr, int na, T* Dc, double* G64, T* Gc, int t, int nt) {
-  for (int e = t; e < mr * na; e += nt) Dc[e] = (T)D[e];
-  for (int e = t; e < na * na; e += nt) {
-    const int i = e % na, j = e / na;
-    double v = 0.0;
-    for (int p = 0; p < mr; ++p) v += D[p + mr * i] * D[p + mr * j];
-    G64[e] = v;
-    Gc[e] = (T)v;
-  }
-}
 
 // LDS bytes the block solve needs for na atoms and mr rows: the augmented system
 // (na rows of na + mr entries, padded), the new dictionary, the pivots' reference
