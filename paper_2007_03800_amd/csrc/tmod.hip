@@ -65,9 +65,9 @@ __global__ void __launch_bounds__(kSolveThreads)
   solve_update_block<T>(sums, mr, na, D, Dc, G64, Gc, w, status, counters, smem_raw, tid, blockDim.x);
 }
 
-// The dictionary's copies and Gram matrix (as write_copies), with D staged in LDS at an odd
-// column stride first: the Gram entries then read LDS without bank conflicts instead of
-// global memory.
+// The dictionary's compute-type copy and its Gram matrix (FP64 and compute type), with D
+// staged in LDS at an odd column stride first: the Gram entries then read LDS without bank
+// conflicts instead of global memory.
 template <typename T>
 __global__ void dict_prep_kernel(const double* D, int mr, int na, T* Dc, double* G64, T* Gc) {
   __shared__ double sD[(SDL_MAX_M + 1) * SDL_MAX_N];
