@@ -201,7 +201,8 @@ int sdl_proposer_set_params(sdl_proposer* p, const float* host);      /* also re
 int sdl_proposer_gradient(sdl_proposer* p, const float* Y, const int32_t* supp, int32_t s, int64_t B,
                           float* grad_host, double* loss_host, void* stream);
 /* Adam (lr, 0.9, 0.999, 1e-8) over `epochs` passes of floor(N/batch) shuffled batches;
- * loss_trace (host, epochs, may be NULL) gets each epoch's mean batch loss. */
+ * loss_trace (host, epochs, may be NULL) gets each epoch's mean batch loss.  SDL_E_SHAPE
+ * unless batch is a positive multiple of 64, batch <= N <= 2^31 - 1 and epochs >= 0. */
 int sdl_proposer_train(sdl_proposer* p, const float* Y, const int32_t* supp, int32_t s, int64_t N, int32_t epochs,
                        int32_t batch, float lr, uint64_t seed, double* loss_trace, void* stream);
 /* Logits of N signals (asynchronous on stream). */

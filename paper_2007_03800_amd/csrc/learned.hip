@@ -300,6 +300,7 @@ int sdl_proposer_train(sdl_proposer* P, const float* Y, const int32_t* supp, int
   if (!P || !Y || !supp) return abi_fail(SDL_E_INVAL, "NULL argument");
   ST(check_shape(P, s));
   if (batch <= 0 || batch % 64 || N < batch || epochs < 0) return abi_fail(SDL_E_SHAPE, "need N >= batch, batch % 64 == 0");
+  if (N > INT32_MAX) return abi_fail(SDL_E_SHAPE, "N > 2^31 - 1 (batch indices are 32-bit)");
   hipStream_t st = (hipStream_t)stream;
   ST(ensure_batch(P, batch));
   if (P->idx_cap < N) {
@@ -311,6 +312,10 @@ int sdl_proposer_train(sdl_proposer* P, const float* Y, const int32_t* supp, int
   std::vector<double> ep_loss;
   double* dloss = nullptr;
   ST(dalloc(&dloss, (size_t)(nb > 0 ? nb : 1)));
+  struct FreeOnExit {  // per-batch losses, released on every return path
+    double* p;
+    ~FreeOnExit() { (void)hipFree(p); }
+  } dloss_guard{dloss};
   for (int ep = 0; ep < epochs; ++ep) {
     // batch order: Fisher-Yates with a counter-based generator (stream 8)
     for (int64_t i = 0; i < N; ++i) perm[i] = (int32_t)i;
@@ -337,7 +342,6 @@ int sdl_proposer_train(sdl_proposer* P, const float* Y, const int32_t* supp, int
       loss_trace[ep] = nb > 0 ? acc / nb : 0.0;
     }
   }
-  (void)hipFree(dloss);
   return SDL_OK;
 }
 
