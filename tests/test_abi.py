@@ -93,3 +93,14 @@ def test_probe_validation():
     assert lib.sdl_probe_peak(4, 1, 1, ctypes.byref(d), None) == -1
     assert lib.sdl_probe_peak(0, None, 1, ctypes.byref(d), None) == -1
     assert lib.sdl_probe_peak(0, 1, 0, ctypes.byref(d), None) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library every call raises: the package has no CPU fallback."""
+    monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "libsdl.so"))
+    monkeypatch.setattr(_native, "_lib", None)
+    with pytest.raises(ImportError):
+        _native.lib()
+    from paper_2007_03800_amd import api
+    with pytest.raises(ImportError):
+        api.tuned_config(8, 8, 16, 16, 8)
