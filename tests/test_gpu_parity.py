@@ -161,6 +161,52 @@ def test_learn_fp32_tracks_oracle(rng):
     np.testing.assert_allclose(tr, ref["rmse"], rtol=0.01)
 
 
+def test_fp32_workload_full_size():
+    """The image-patch workload at its full size (100,000 FP32 signals), run as the benchmark runs it
+    (autotuned kernel, Algorithm 1 in captured graphs, sums fused into the sparse coding): the RMSE
+    trace against the oracle's Algorithm 1 on the same (FP32-rounded) signals; sampled final codes
+    (first and last 1000 signals, 1000 random ones) against the oracle's 2D-OMP at the GPU's final
+    dictionaries; one D1 update from the full batch's codes against the oracle's FP64 update."""
+    w = synth.WORKLOADS["fp32_8x8_n16_s8"]
+    Ycm = synth.signals(w, 0, w.N, layout="colmajor").astype(np.float32)
+    Ym = Ycm.astype(np.float64).transpose(0, 2, 1)  # (N, m1, m2), exactly the GPU's input values
+    d1, d2 = synth.initial_dictionaries(w)
+    Y = torch.from_numpy(Ycm).to(DEV).contiguous()
+
+    def fresh():
+        return api.Problem(Y, torch.from_numpy(d1.T.copy()).to(DEV), torch.from_numpy(d2.T.copy()).to(DEV), w.s)
+
+    api.autotune(fresh(), reps=2)
+    K = 3
+    pr = fresh()
+    tr = api.learn(pr, K)[0]
+    torch.cuda.synchronize()
+    ref = oracle.learn(Ym, d1, d2, w.s, K, p=8)
+    print("rmse gpu", tr, "oracle", ref["rmse"])
+    np.testing.assert_allclose(tr, ref["rmse"], rtol=0.01)
+
+    e1, e2 = pr.d1(), pr.d2()
+    sg, cg = pr.supp.cpu().numpy(), pr.coef.cpu().double().numpy()
+    rs = np.random.default_rng(11)
+    idx = np.unique(np.concatenate([np.arange(1000), np.arange(w.N - 1000, w.N), rs.choice(w.N, 1000, replace=False)]))
+    so, co, _ = oracle.omp(Ym[idx], e1, e2, w.s)
+    agree, ties, bad, err = compare_codes(Ym[idx], e1, e2, sg[idx], cg[idx], so, co, 1e-4, 1e-4)
+    n = len(idx)
+    print("sampled support agreement %d/%d, near-ties %d, other %d, coef err %.2e" % (agree, n, ties, bad, err))
+    assert agree >= 0.99 * n and bad <= 5 and err <= 1e-4
+
+    u1, _, _, _ = oracle.tmod_update(1, Ym, e1, e2, sg, cg)
+    pu = fresh()
+    pu.D1.copy_(pr.D1)
+    pu.D2.copy_(pr.D2)
+    pu.supp.copy_(pr.supp)
+    pu.coef.copy_(pr.coef)
+    api.tmod_update(pu, sides=1)
+    torch.cuda.synchronize()
+    print("full-batch D1 update max abs diff %.2e" % np.abs(pu.d1() - u1).max())
+    np.testing.assert_allclose(pu.d1(), u1, rtol=1e-4, atol=1e-4)
+
+
 # ------------------------------------------------------------------ edge cases
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
