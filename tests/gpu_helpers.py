@@ -42,3 +42,37 @@ def compare_codes(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band, coef_rtol):
         den = np.abs(coef_o[agree]).max(axis=1) + 1e-300
         err = float((num / den).max())
     return int(agree.sum()), ties, bad, err
+
+
+def full_size_checks(Ym, pr, s, fresh, n_each=1000, seed=11):
+    """Checks of a problem coded at full size on the GPU (``pr``, after Algorithm 1), against
+    the oracle on ``Ym`` (N, m1, m2): exactly the signal values the GPU read, in FP64.
+
+    * Sampled final codes (the first and last ``n_each`` signals and ``n_each`` random ones)
+      against the oracle's 2D-OMP at the GPU's final dictionaries.
+    * One D1 update from the GPU's full-batch codes, on a fresh problem built by ``fresh``
+      with the same dictionaries and codes, against the oracle's FP64 update.
+
+    Returns (n_sampled, n_agree, n_near_tie, n_bad, max coef rel err, max |D1 diff|)."""
+    import torch
+
+    import oracle
+    from paper_2007_03800_amd import api
+
+    N = len(Ym)
+    e1, e2 = pr.d1(), pr.d2()
+    sg, cg = pr.supp.cpu().numpy(), pr.coef.cpu().double().numpy()
+    rs = np.random.default_rng(seed)
+    k = min(n_each, N)
+    idx = np.unique(np.concatenate([np.arange(k), np.arange(N - k, N), rs.choice(N, k, replace=False)]))
+    so, co, _ = oracle.omp(Ym[idx], e1, e2, s, p=8)
+    agree, ties, bad, err = compare_codes(Ym[idx], e1, e2, sg[idx], cg[idx], so, co, 1e-4, 1e-4)
+    u1 = oracle.tmod_update(1, Ym, e1, e2, sg, cg, p=8)[0]
+    pu = fresh()
+    pu.D1.copy_(pr.D1)
+    pu.D2.copy_(pr.D2)
+    pu.supp.copy_(pr.supp)
+    pu.coef.copy_(pr.coef)
+    api.tmod_update(pu, sides=1)
+    torch.cuda.synchronize()
+    return len(idx), agree, ties, bad, err, float(np.abs(pu.d1() - u1).max())

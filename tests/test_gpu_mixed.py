@@ -13,9 +13,11 @@ import oracle
 from paper_2007_03800_amd import api, synth
 from paper_2007_03800_amd._native import SdlError
 from tests.conftest import planted, rand_dicts
-from tests.gpu_helpers import compare_codes
+from tests.gpu_helpers import compare_codes, full_size_checks
 
 pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
 
 
 def rounded(Y):
@@ -79,6 +81,31 @@ def test_mixed_workload_matches_oracle_on_rounded_signals():
     tr = api.learn(pr, K)[0]
     print("rmse gpu", tr, "oracle", ref["rmse"])
     np.testing.assert_allclose(tr, ref["rmse"], rtol=0.01)
+
+
+def test_mixed_workload_full_size():
+    """The mixed-precision workload at its full size (1,000,000 BF16 signals), run as the benchmark
+    runs it (autotuned kernel, Algorithm 1 in captured graphs): sampled final codes against the
+    oracle's 2D-OMP on the rounded signals at the GPU's final dictionaries, and one full-batch D1
+    update from identical codes against the oracle's FP64 update."""
+    w = synth.WORKLOADS["mixed_12x12_n24_s12"]
+    Yb = torch.from_numpy(synth.signals(w, 0, w.N, layout="colmajor")).to(torch.bfloat16)
+    Ym = Yb.double().numpy().transpose(0, 2, 1)  # (N, m1, m2): the values the GPU reads
+    Y = Yb.to(DEV).contiguous()
+    e1, e2 = synth.initial_dictionaries(w)
+
+    def fresh():
+        return api.Problem(Y, torch.from_numpy(e1.T.copy()).to(DEV), torch.from_numpy(e2.T.copy()).to(DEV), w.s)
+
+    api.autotune(fresh(), reps=2)
+    pr = fresh()
+    api.learn(pr, 2)
+    torch.cuda.synchronize()
+    n, agree, ties, bad, err, dd = full_size_checks(Ym, pr, w.s, fresh)
+    print("sampled support agreement %d/%d, near-ties %d, other %d, coef err %.2e; full-batch D1 update max "
+          "abs diff %.2e" % (agree, n, ties, bad, err, dd))
+    assert agree >= 0.97 * n and bad <= 5 and err <= 2e-4
+    assert dd <= 1e-4
 
 
 def test_nonfinite_bf16_input_reported(rng):

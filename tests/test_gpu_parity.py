@@ -15,7 +15,7 @@ import oracle
 from paper_2007_03800_amd import api, synth
 from paper_2007_03800_amd._native import SdlError
 from tests.conftest import planted, rand_dicts
-from tests.gpu_helpers import compare_codes
+from tests.gpu_helpers import compare_codes, full_size_checks
 
 pytestmark = pytest.mark.gpu
 
@@ -185,26 +185,39 @@ def test_fp32_workload_full_size():
     print("rmse gpu", tr, "oracle", ref["rmse"])
     np.testing.assert_allclose(tr, ref["rmse"], rtol=0.01)
 
-    e1, e2 = pr.d1(), pr.d2()
-    sg, cg = pr.supp.cpu().numpy(), pr.coef.cpu().double().numpy()
-    rs = np.random.default_rng(11)
-    idx = np.unique(np.concatenate([np.arange(1000), np.arange(w.N - 1000, w.N), rs.choice(w.N, 1000, replace=False)]))
-    so, co, _ = oracle.omp(Ym[idx], e1, e2, w.s)
-    agree, ties, bad, err = compare_codes(Ym[idx], e1, e2, sg[idx], cg[idx], so, co, 1e-4, 1e-4)
-    n = len(idx)
-    print("sampled support agreement %d/%d, near-ties %d, other %d, coef err %.2e" % (agree, n, ties, bad, err))
+    n, agree, ties, bad, err, dd = full_size_checks(Ym, pr, w.s, fresh)
+    print("sampled support agreement %d/%d, near-ties %d, other %d, coef err %.2e; full-batch D1 update max "
+          "abs diff %.2e" % (agree, n, ties, bad, err, dd))
     assert agree >= 0.99 * n and bad <= 5 and err <= 1e-4
+    assert dd <= 1e-4
 
-    u1, _, _, _ = oracle.tmod_update(1, Ym, e1, e2, sg, cg)
-    pu = fresh()
-    pu.D1.copy_(pr.D1)
-    pu.D2.copy_(pr.D2)
-    pu.supp.copy_(pr.supp)
-    pu.coef.copy_(pr.coef)
-    api.tmod_update(pu, sides=1)
+
+def test_uneven_batch_full_size():
+    """The uneven batch at its full sizes (200k + 100k + 50k + 20k signals of four shapes), run as the
+    benchmark runs it (autotuned kernels, one Algorithm 1 call whose problems are concurrent graph
+    branches), for every problem: sampled final codes against the oracle's 2D-OMP at that problem's
+    final dictionaries, and one full-batch D1 update from identical codes against the oracle's."""
+    ws = [synth.WORKLOADS[n] for n in synth.UNEVEN_BATCH]
+    Ycm = [synth.signals(w, 0, w.N, layout="colmajor").astype(np.float32) for w in ws]
+    Yd = [torch.from_numpy(y).to(DEV).contiguous() for y in Ycm]
+    dd0 = [synth.initial_dictionaries(w) for w in ws]
+
+    def fresh_one(q):
+        d1, d2 = dd0[q]
+        return api.Problem(Yd[q], torch.from_numpy(d1.T.copy()).to(DEV), torch.from_numpy(d2.T.copy()).to(DEV),
+                           ws[q].s)
+
+    api.autotune([fresh_one(q) for q in range(4)], reps=2)
+    probs = [fresh_one(q) for q in range(4)]
+    api.learn(probs, 2)
     torch.cuda.synchronize()
-    print("full-batch D1 update max abs diff %.2e" % np.abs(pu.d1() - u1).max())
-    np.testing.assert_allclose(pu.d1(), u1, rtol=1e-4, atol=1e-4)
+    for q, w in enumerate(ws):
+        Ym = Ycm[q].astype(np.float64).transpose(0, 2, 1)
+        n, agree, ties, bad, err, dd = full_size_checks(Ym, probs[q], w.s, lambda: fresh_one(q), n_each=400)
+        print("%s: sampled support agreement %d/%d, near-ties %d, other %d, coef err %.2e; D1 update diff %.2e"
+              % (w.name, agree, n, ties, bad, err, dd))
+        assert agree >= 0.97 * n and bad <= 5 and err <= 2e-4
+        assert dd <= 1e-4
 
 
 # ------------------------------------------------------------------ edge cases
