@@ -128,10 +128,11 @@ __global__ void __launch_bounds__(kWave* kWaves) tmod_sums_kernel(TmodArgs<T> a,
       for (int i = 0; i < TP; ++i) at[i] = Tb[k * NP + 16 * i + r16];
 #pragma unroll
       for (int i = 0; i < TR; ++i) ay[i] = Yt[k * MP + 16 * i + r16];
+      // P is symmetric: its diagonal and upper 16x16 tiles only (the write-out mirrors the rest)
 #pragma unroll
       for (int i = 0; i < TP; ++i)
 #pragma unroll
-        for (int j = 0; j < TP; ++j) accP[i][j] = MF::step(at[i], at[j], accP[i][j]);
+        for (int j = i; j < TP; ++j) accP[i][j] = MF::step(at[i], at[j], accP[i][j]);
 #pragma unroll
       for (int i = 0; i < TR; ++i)
 #pragma unroll
@@ -149,11 +150,14 @@ __global__ void __launch_bounds__(kWave* kWaves) tmod_sums_kernel(TmodArgs<T> a,
 #pragma unroll
     for (int i = 0; i < TP; ++i)
 #pragma unroll
-      for (int j = 0; j < TP; ++j)
+      for (int j = i; j < TP; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = 16 * i + MF::row(lane, v), c = 16 * j + col;
-          if (r < na && c < na) red[w * nent + r + na * c] = accP[i][j][v];
+          if (r < na && c < na) {
+            red[w * nent + r + na * c] = accP[i][j][v];
+            if (j > i) red[w * nent + c + na * r] = accP[i][j][v];
+          }
         }
 #pragma unroll
     for (int i = 0; i < TR; ++i)
