@@ -51,11 +51,12 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         i32, i64, dp, ip, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double
         lib.sdlref_omp.argtypes = [i32, i32, i32, i32, i32, i32, i64, dp, dp, dp, ip, dp, dp, f64, f64, i32]
+        lib.sdlref_omp_err.argtypes = [i32, i32, i32, i32, i32, i32, i64, dp, dp, dp, ip, dp, dp, f64, f64, f64, i32]
         lib.sdlref_tmod_sums.argtypes = [i32, i32, i32, i32, i32, i32, i64, dp, dp, dp, ip, dp, i32, dp, dp]
         lib.sdlref_tmod_update.argtypes = [i32, i32, i32, i32, i32, i32, i64, dp, dp, dp, ip, dp, i32, dp]
         lib.sdlref_learn.argtypes = [i32, i32, i32, i32, i32, i64, i32, i32, dp, dp, dp, ip, dp, dp, dp,
                                      f64, f64, i32]
-        for f in (lib.sdlref_omp, lib.sdlref_tmod_sums, lib.sdlref_tmod_update, lib.sdlref_learn):
+        for f in (lib.sdlref_omp, lib.sdlref_omp_err, lib.sdlref_tmod_sums, lib.sdlref_tmod_update, lib.sdlref_learn):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -81,8 +82,9 @@ def _check(st):
         raise OracleError(st)
 
 
-def omp(Y, D1, D2, s, mode="separable", p=1, stop_rel=STOP_REL, dep_eps=DEP_EPS):
-    """2D-OMP of every signal.  Returns (supp, coef, res2)."""
+def omp(Y, D1, D2, s, mode="separable", p=1, stop_rel=STOP_REL, dep_eps=DEP_EPS, err2=0.0):
+    """2D-OMP of every signal.  Returns (supp, coef, res2).  err2 > 0: error-driven stop
+    (Sec. IV's denoising runs): a signal takes no further atom once ||R_k||_F^2 <= err2."""
     Y = np.asarray(Y, np.float64)
     N, m1, m2 = Y.shape
     n1, n2 = D1.shape[1], D2.shape[1]
@@ -90,8 +92,8 @@ def omp(Y, D1, D2, s, mode="separable", p=1, stop_rel=STOP_REL, dep_eps=DEP_EPS)
     supp = np.empty((N, s), np.int32)
     coef = np.empty((N, s), np.float64)
     res2 = np.empty(N, np.float64)
-    st = _load().sdlref_omp(0 if mode == "separable" else 1, m1, m2, n1, n2, s, N, _ptr(Yc), _ptr(D1c),
-                            _ptr(D2c), _ptr(supp), _ptr(coef), _ptr(res2), stop_rel, dep_eps, p)
+    st = _load().sdlref_omp_err(0 if mode == "separable" else 1, m1, m2, n1, n2, s, N, _ptr(Yc), _ptr(D1c),
+                                _ptr(D2c), _ptr(supp), _ptr(coef), _ptr(res2), stop_rel, dep_eps, err2, p)
     _check(st)
     return supp, coef, res2
 

@@ -115,7 +115,17 @@ static double bilinear(const double* D1, const double* D2, int m1, int m2, int i
 typedef struct {
   int m1, m2, n1, n2, s;
   double stop_rel, dep_eps;
+  double err2; /* error-driven stop: ||r||_F^2 <= err2 ends the signal (off when <= 0) */
 } omp_cfg;
+
+/* Error-driven OMP (the denoising experiments, Sec. IV): no further atom once the
+ * residual's energy is at or below the target. */
+static int residual_small(const omp_cfg* c, const double* r, int M) {
+  if (!(c->err2 > 0.0)) return 0;
+  double v = 0.0;
+  for (int e = 0; e < M; ++e) v += r[e] * r[e];
+  return v <= c->err2;
+}
 
 /* One signal.  work: m1*m2 (r) + n1*m2 (tmp) + n1*n2 (alpha) + (s)^2 (G) + s (x) doubles,
  * plus n1*n2 bytes for the selection mask. */
@@ -138,6 +148,7 @@ static void omp_sep_one(const omp_cfg* c, const double* Y, const double* D1, con
 
   int t = 0;
   for (int step = 0; step < s; ++step) {
+    if (residual_small(c, r, M)) break;
     /* correlations of the residual with every atom: alpha = D1^T r D2 */
     for (int q = 0; q < m2; ++q)
       for (int i = 0; i < n1; ++i) {
@@ -265,6 +276,7 @@ static void omp_kron_one(const omp_cfg* c, const double* Kd /* M x A */, const d
   ynorm = sqrt(ynorm);
   int t = 0;
   for (int step = 0; step < s; ++step) {
+    if (residual_small(c, r, M)) break;
     for (int a = 0; a < A; ++a) {
       double v = 0.0;
       for (int e = 0; e < M; ++e) v += Kd[(size_t)M * a + e] * r[e];
@@ -305,12 +317,19 @@ int sdlref_omp(int mode, int m1, int m2, int n1, int n2, int s, int64_t N,
                const double* Y, const double* D1, const double* D2,
                int32_t* supp, double* coef, double* res2,
                double stop_rel, double dep_eps, int p) {
+  return sdlref_omp_err(mode, m1, m2, n1, n2, s, N, Y, D1, D2, supp, coef, res2, stop_rel, dep_eps, 0.0, p);
+}
+
+int sdlref_omp_err(int mode, int m1, int m2, int n1, int n2, int s, int64_t N,
+                   const double* Y, const double* D1, const double* D2,
+                   int32_t* supp, double* coef, double* res2,
+                   double stop_rel, double dep_eps, double err2, int p) {
   int st = check_dims(m1, m2, n1, n2, s, N);
   if (st) return st;
   if ((N > 0 && (!Y || !supp || !coef)) || !D1 || !D2 || p <= 0 || (mode != 0 && mode != 1))
     return REF_E_INVAL;
   const int M = m1 * m2, A = n1 * n2;
-  omp_cfg c = {m1, m2, n1, n2, s, stop_rel, dep_eps};
+  omp_cfg c = {m1, m2, n1, n2, s, stop_rel, dep_eps, err2};
   double* Kd = NULL;
   if (mode == 1) {
     /* explicit Kronecker dictionary: column a = i + n1 j is vec(d1_i d2_j^T) = d2_j (x) d1_i */

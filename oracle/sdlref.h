@@ -28,6 +28,13 @@ int sdlref_omp(int mode, int m1, int m2, int n1, int n2, int s, int64_t N,
                const double* Y, const double* D1, const double* D2,
                int32_t* supp, double* coef, double* res2,
                double stop_rel, double dep_eps, int p);
+/* The same with the error-driven stop of the denoising experiments (Sec. IV): before each
+ * step, a signal whose residual energy ||R_k||_F^2 is <= err2 takes no further atom (err2 <= 0:
+ * off, identical to sdlref_omp).  The atom cap is s. */
+int sdlref_omp_err(int mode, int m1, int m2, int n1, int n2, int s, int64_t N,
+                   const double* Y, const double* D1, const double* D2,
+                   int32_t* supp, double* coef, double* res2,
+                   double stop_rel, double dep_eps, double err2, int p);
 
 /* Dense partial sums of one TMOD half-step, by their definitions.
  * side 1 (Corollary 1): T_k = X_k D2^T;  A = sum T_k T_k^T (n1 x n1),

@@ -202,3 +202,64 @@ def test_shards_do_not_change_codes(rng):
     b = oracle.omp(Y, d1, d2, 4, p=7)
     for u, v in zip(a, b):
         np.testing.assert_array_equal(u, v)
+
+
+# ---------------------------------------------------------------- error-driven stop (Sec. IV)
+
+def test_error_driven_orthonormal_closed_form(rng):
+    """Orthogonal D1, D2 (Remark 1): the greedy order is decreasing |D1^T Y D2|, so the
+    error-driven code has the smallest t whose tail energy sum_{u>t} C_(u)^2 is <= eps^2
+    (capped at s), on the first t entries of that order."""
+    m, s = 8, 32  # cap m^2 / 2, as in the denoising runs
+    d1 = np.linalg.qr(rng.standard_normal((m, m)))[0]
+    d2 = np.linalg.qr(rng.standard_normal((m, m)))[0]
+    Y = rng.standard_normal((40, m, m)) * rng.uniform(0.2, 2.0, (40, 1, 1))
+    sigma = 0.5
+    err2 = (1.15 * sigma * m) ** 2  # eps = 1.15 sigma sqrt(m1 m2)
+    supp, coef, res2 = oracle.omp(Y, d1, d2, s, err2=err2)
+    nnz_seen = set()
+    for k in range(len(Y)):
+        C = (d1.T @ Y[k] @ d2).flatten("F")
+        order = np.argsort(-np.abs(C), kind="stable")
+        tail = np.sum(Y[k] ** 2) - np.concatenate([[0.0], np.cumsum(C[order] ** 2)])  # energy after t atoms
+        t = min(int(np.argmax(tail <= err2)) if np.any(tail <= err2) else s, s)
+        nnz = int(np.sum(supp[k] >= 0))
+        nnz_seen.add(nnz)
+        assert nnz == t, (k, nnz, t)
+        assert list(supp[k, :t]) == list(order[:t])
+        np.testing.assert_allclose(coef[k, :t], C[order[:t]], rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(res2[k], tail[t], rtol=1e-9, atol=1e-12)
+    assert len(nnz_seen) > 3  # the stop really varies per signal
+
+
+def test_error_driven_equals_kronecker_omp_and_is_minimal(rng):
+    """General dictionaries: the separable error-driven 2D-OMP equals textbook 1D OMP with the
+    same stop on the explicit Kronecker dictionary; a signal that stopped before the cap is
+    within eps^2, and the same greedy run one atom shorter is not."""
+    d1, d2 = rand_dicts(rng, 6, 7, 9, 11)
+    Y, _ = planted(rng, 80, d1, d2, 8, noise=0.3)
+    s = 21
+    err2 = float(np.median(np.sum(Y ** 2, axis=(1, 2)))) * 0.05
+    a = oracle.omp(Y, d1, d2, s, err2=err2)
+    b = oracle.omp(Y, d1, d2, s, mode="kronecker", err2=err2)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-9, atol=1e-11)
+    nnz = np.sum(a[0] >= 0, axis=1)
+    assert len(set(nnz.tolist())) > 2
+    for t in sorted(set(nnz.tolist())):
+        ks = np.nonzero(nnz == t)[0]
+        if t < s:
+            assert np.all(a[2][ks] <= err2)
+        if t > 0:
+            shorter = oracle.omp(Y[ks], d1, d2, t - 1)
+            assert np.all(shorter[2] > err2)
+            np.testing.assert_array_equal(shorter[0][:, :t - 1], a[0][ks, :t - 1])
+
+
+def test_error_driven_off_is_plain_omp(rng):
+    d1, d2 = rand_dicts(rng, 5, 6, 8, 9)
+    Y, _ = planted(rng, 30, d1, d2, 4, noise=0.2)
+    a = oracle.omp(Y, d1, d2, 6)
+    b = oracle.omp(Y, d1, d2, 6, err2=0.0)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
