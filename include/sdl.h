@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SDL_ABI_VERSION 3
+#define SDL_ABI_VERSION 4
 
 typedef enum { SDL_FP64 = 0, SDL_FP32 = 1, SDL_BF16 = 2 } sdl_prec;
 
@@ -112,6 +112,12 @@ typedef struct sdl_options {
   sdl_stats* stats;         /* host, optional */
   sdl_proposer* proposer;   /* sdl_learn: code with the learned proposal + 2D-OMP fallback (NULL = plain) */
   double tau;               /* acceptance threshold of the proposal: ||r||^2 <= tau*||Y||^2 (default 0) */
+  double err2;              /* error-driven stop of the denoising experiments (Sec. IV): before each
+                               greedy step, a signal whose residual energy ||Y_k - D1 X_k D2^T||_F^2 is
+                               <= err2 takes no further atom; s stays the cap (the paper uses
+                               eps = 1.15 sigma sqrt(m1 m2), err2 = eps^2, s = m1 m2 / 2).  0 = off
+                               (default); negative or NaN: SDL_E_INVAL.  Runs on the generic kernel:
+                               kernel 2 or 3, or a learned proposal, with err2 > 0 is SDL_E_UNSUPPORTED */
 } sdl_options;
 
 /* Fill *o with the defaults above (prec = SDL_FP64).  Passing NULL options to the

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("schedule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("timing", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("stop_rel", ctypes.c_double), ("dep_eps", ctypes.c_double), ("pivot_fp64", ctypes.c_double),
-                ("stats", ctypes.POINTER(Stats)), ("proposer", ctypes.c_void_p), ("tau", ctypes.c_double)]
+                ("stats", ctypes.POINTER(Stats)), ("proposer", ctypes.c_void_p), ("tau", ctypes.c_double),
+                ("err2", ctypes.c_double)]
 
 
 class SdlError(RuntimeError):

@@ -108,7 +108,10 @@ __global__ void __launch_bounds__(kWave) omp_generic_kernel(OmpArgs<T> a) {
       yy += v * v;
     }
     for (int e = lane; e < A; e += kWave) sel[e] = 0;
-    const T ynorm = sqrt(wave_sum(yy));
+    const T yy_all = wave_sum(yy);
+    const T ynorm = sqrt(yy_all);
+    // residual energy, by the OMP recurrence ||r||^2 -= corr_a^2 / pivot per appended atom
+    T renergy = yy_all;
     __syncthreads();
     // C = D1^T Y D2, as W = D1^T Y (n1 x m2) then W D2
     for (int e = lane; e < n1 * m2; e += kWave) {
@@ -129,6 +132,11 @@ __global__ void __launch_bounds__(kWave) omp_generic_kernel(OmpArgs<T> a) {
     int t = 0;
     bool early = false;
     for (; t < s; ++t) {
+      // error-driven stop (denoising runs, Sec. IV): no further atom once ||r||^2 <= err2
+      if (a.err2 > 0.0 && !(renergy > T(a.err2))) {
+        early = true;
+        break;
+      }
       // greedy choice
       T bv = T(-1);
       int bi = INT_MAX;
@@ -176,6 +184,7 @@ __global__ void __launch_bounds__(kWave) omp_generic_kernel(OmpArgs<T> a) {
         vs[q] = b / Ls[q * s + q];
       }
       const T cstar = al[bi] / d2;
+      renergy -= cstar * al[bi];
       __syncthreads();
       if (lane == 0) {
         for (int q = 0; q < t; ++q) {

@@ -129,6 +129,7 @@ struct Opt {
   sdl_stats* stats;
   sdl_proposer* proposer;
   double tau;
+  double err2;
 };
 
 Opt resolve(const sdl_options* o) {
@@ -148,6 +149,7 @@ Opt resolve(const sdl_options* o) {
   r.stats = o->stats;
   r.proposer = o->proposer;
   r.tau = o->tau;
+  r.err2 = o->err2;
   return r;
 }
 
@@ -158,6 +160,9 @@ int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_
     return fail(SDL_E_INVAL, "prec = %d is not an sdl_prec", o.prec);
   if (o.schedule != 0 && o.schedule != 1) return fail(SDL_E_INVAL, "schedule = %d (0 or 1)", o.schedule);
   if (o.kernel < 0 || o.kernel > 3) return fail(SDL_E_INVAL, "kernel = %d (0..3)", o.kernel);
+  if (!(o.err2 >= 0.0)) return fail(SDL_E_INVAL, "err2 must be >= 0 (0: off)");
+  if (o.err2 > 0.0 && (o.kernel == 2 || o.kernel == 3))
+    return fail(SDL_E_UNSUPPORTED, "the error-driven stop runs on the generic kernel (kernel 0 or 1)");
   const size_t elem = o.prec == SDL_FP64 ? 8 : 4;
   for (int q = 0; q < nprob; ++q) {
     const sdl_problem& r = p[q];
@@ -298,6 +303,7 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
   a.stop_rel = o.stop_rel;
   a.dep_eps = o.dep_eps;
   a.pivot_fp64 = o.pivot_fp64;
+  a.err2 = o.err2;
   a.counters = pl.counters;
   a.sums_side = 0;
   a.sums_part = nullptr;
@@ -308,7 +314,7 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
 
 template <typename T>
 bool use_fast(const sdl_problem& r, const Opt& o) {
-  if (!omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s)) return false;
+  if (!omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s) || o.err2 > 0.0) return false;
   return o.kernel == 2 || (o.kernel == 0 && !wave_chosen(r.m1, r.m2, r.n1, r.n2, r.s));
 }
 
@@ -323,7 +329,7 @@ int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, i
   if (o.kernel == 2 && !fast)
     return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for m=%dx%d n=%dx%d s=%d in this precision", r.m1,
                 r.m2, r.n1, r.n2, r.s);
-  const bool wave = !fast && sums_side == 0 && (o.kernel == 0 || o.kernel == 3) &&
+  const bool wave = !fast && sums_side == 0 && (o.kernel == 0 || o.kernel == 3) && !(o.err2 > 0.0) &&
                     omp_wave_supported(r.m1, r.m2, r.n1, r.n2, r.s);
   if (o.kernel == 3 && !wave)
     return fail(SDL_E_UNSUPPORTED, "no one-wave-per-signal kernel for m=%dx%d n=%dx%d s=%d", r.m1, r.m2, r.n1, r.n2,
@@ -507,6 +513,7 @@ int tmod_update_impl(sdl_problem* p, int nprob, uint32_t sides, const Opt& o, hi
 
 int validate_learned(const sdl_problem* p, int nprob, const Opt& o) {
   if (!o.proposer) return SDL_OK;
+  if (o.err2 > 0.0) return fail(SDL_E_UNSUPPORTED, "the error-driven stop does not apply to the learned proposal");
   if (o.prec != SDL_FP32) return fail(SDL_E_UNSUPPORTED, "the learned proposal runs on FP32 problems");
   for (int q = 0; q < nprob; ++q) {
     if (!proposer_matches(o.proposer, p[q]))
@@ -728,6 +735,7 @@ void sdl_default_options(sdl_options* o) {
   o->stats = nullptr;
   o->proposer = nullptr;
   o->tau = 0.0;
+  o->err2 = 0.0;
 }
 
 int sdl_sparse_code(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream) {

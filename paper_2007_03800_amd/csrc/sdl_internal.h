@@ -32,6 +32,7 @@ struct OmpArgs {
   T* coef;
   T* res2;  // may be null
   double stop_rel, dep_eps, pivot_fp64;
+  double err2;  // > 0: error-driven stop (generic kernel only), residual energy target
   unsigned long long* counters;  // kNumCounters entries
   // Register-resident kernel only: also accumulate the TMOD sums of the new codes for
   // side sums_side (1: D1 update, 2: D2 update; 0: none) plus the sum of res2, one

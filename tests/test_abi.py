@@ -20,7 +20,7 @@ def test_header_symbols_exported():
     lib = _native.lib()
     for n in names:
         assert hasattr(lib, n)
-    assert lib.sdl_abi_version() == 3
+    assert lib.sdl_abi_version() == 4
 
 
 def _problem(**kw):
@@ -82,6 +82,20 @@ def test_default_options():
     o = _native.default_options()
     assert o.prec == 0 and o.use_graph == 1 and o.schedule == 0
     assert o.stop_rel < 0 and o.dep_eps < 0 and o.pivot_fp64 < 0
+    assert o.err2 == 0.0
+
+
+def test_error_driven_option_validation():
+    """err2 < 0 or NaN is invalid; err2 > 0 needs the generic kernel (checked before device work)."""
+    for bad in (-1.0, float("nan")):
+        o = _native.default_options()
+        o.err2 = bad
+        assert _call("sparse_code", _problem(), o) == -1
+    for kern in (2, 3):
+        o = _native.default_options()
+        o.err2 = 1.0
+        o.kernel = kern
+        assert _call("sparse_code", _problem(), o) == -7
 
 
 def test_probe_validation():
