@@ -44,6 +44,9 @@ static int run(int m1, int m2, int n1, int n2, int s, int64_t N) {
     for (int64_t e = 0; e < M; ++e) Y[M + e] = 0.0; /* a zero signal */
   for (int mode = 0; mode < 2; ++mode)
     bad |= sdlref_omp(mode, m1, m2, n1, n2, s, N, Y, D1, D2, supp, coef, res2, 1e-14, 1e-10, 2) != 0;
+  for (int mode = 0; mode < 2; ++mode) /* error-driven stop at about a third of a signal's energy */
+    bad |= sdlref_omp_err(mode, m1, m2, n1, n2, s, N, Y, D1, D2, supp, coef, res2, 1e-14, 1e-10, 0.1 * (double)M,
+                          2) != 0;
   for (int side = 1; side <= 2; ++side) {
     bad |= sdlref_tmod_sums(side, m1, m2, n1, n2, s, N, Y, D1, D2, supp, coef, 2, A, B) != 0;
     const int st = sdlref_tmod_update(side, m1, m2, n1, n2, s, N, Y, D1, D2, supp, coef, 2, w);
