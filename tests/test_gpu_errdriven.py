@@ -67,3 +67,36 @@ def test_error_driven_off_matches_plain():
     api.sparse_code(b, err2=0.0)
     torch.cuda.synchronize()
     assert torch.equal(a.supp, b.supp) and torch.equal(a.coef, b.coef)
+
+
+def _composed_learn(Y, d1, d2, s, K, err2):
+    """Algorithm 1 (OMP, D1 update, OMP, D2 update per iteration) composed from the oracle's
+    calls, with the error-driven stop in every OMP sweep."""
+    e1, e2 = d1, d2
+    for _ in range(K):
+        for side in (1, 2):
+            supp, coef, _ = oracle.omp(Y, e1, e2, s, err2=err2)
+            e1, e2, coef, _ = oracle.tmod_update(side, Y, e1, e2, supp, coef)
+    return e1, e2
+
+
+def test_learn_with_error_driven_stop_fp64(rng):
+    """sdl_learn with err2 > 0 (generic kernel, standalone sums) equals Algorithm 1 composed from
+    the oracle's error-driven OMP and dictionary updates (FP64, 1e-9)."""
+    from tests.conftest import planted, rand_dicts
+    t1, t2 = rand_dicts(rng, 6, 7, 9, 11)
+    Y, _ = planted(rng, 400, t1, t2, 5, noise=0.2)
+    d1, d2 = rand_dicts(rng, 6, 7, 9, 11)
+    s, K = 12, 2
+    err2 = float(np.median(np.sum(Y ** 2, axis=(1, 2)))) * 0.1
+    ref0 = oracle.learn(Y, d1, d2, s, K)  # the composition itself, without the stop, is Algorithm 1
+    c1, c2 = _composed_learn(Y, d1, d2, s, K, 0.0)
+    np.testing.assert_allclose(c1, ref0["D1"], rtol=1e-12, atol=1e-12)
+    e1, e2 = _composed_learn(Y, d1, d2, s, K, err2)
+    pr = api.Problem.from_math(Y, d1, d2, s, dtype=torch.float64, device=DEV)
+    api.learn(pr, K, err2=err2)
+    torch.cuda.synchronize()
+    nnz = np.sum(pr.supp.cpu().numpy() >= 0, axis=1)
+    assert len(set(nnz.tolist())) > 2  # the stop varies per signal
+    np.testing.assert_allclose(pr.d1(), e1, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(pr.d2(), e2, rtol=1e-9, atol=1e-9)
