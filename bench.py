@@ -216,6 +216,38 @@ def mixed_workload(api, oracle, synth):
     return out
 
 
+def error_driven_workload(api, oracle, synth):
+    """Error-driven 2D-OMP (the stopping rule of the paper's denoising runs, Sec. IV) on the plain
+    workload's 100,000 FP32 signals at their true dictionaries: eps = 1.15 sigma sqrt(m1 m2),
+    err2 = eps^2, cap s = m1 m2 / 2, on the generic kernel; one sparse-coding launch timed with
+    HIP events (mean of 5)."""
+    import torch
+    w = synth.WORKLOADS["fp32_8x8_n16_s8"]
+    Y = device_signals(synth, w, torch.float32)
+    d1, d2 = synth.true_dictionaries(w)
+    m = w.m1 * w.m2
+    s = m // 2
+    err2 = float((1.15 * w.sigma() * np.sqrt(m)) ** 2)
+    pr = api.Problem(Y, torch.from_numpy(d1.T.copy()).cuda(), torch.from_numpy(d2.T.copy()).cuda(), s)
+    api.sparse_code(pr, err2=err2)
+    st = api.new_stats()
+    for _ in range(5):
+        api.sparse_code(pr, err2=err2, timing=1, stats=st)
+    torch.cuda.synchronize()
+    d = st.as_dict()
+    ms = d["kernel_ms"]["sparse_code"] / d["kernel_launches"]["sparse_code"]
+    supp = pr.supp.cpu().numpy()
+    nsub = 3000
+    Ysub = Y[:nsub].double().cpu().numpy().transpose(0, 2, 1)
+    s_o, _, _ = oracle.omp(Ysub, d1, d2, s, err2=err2, p=min(16, os.cpu_count() or 1))
+    nbytes = w.N * (4 * m + 8 * s + 4)  # signals in; supp, coef, res2 out
+    return {"workload": w.name + " with the error-driven stop", "N": w.N, "s_cap": s, "err2": err2,
+            "value": w.N / ms * 1e3, "unit": "signals/s", "kernel_ms": ms,
+            "mean_atoms": float((supp >= 0).sum(axis=1).mean()), "max_atoms": int((supp >= 0).sum(axis=1).max()),
+            "hbm_gbs": nbytes / (ms * 1e-3) / 1e9, "omp_kernel": "generic (one wave per signal, all in LDS)",
+            **support_agreement(supp[:nsub], s_o)}
+
+
 def uneven_workload(api, oracle, synth):
     """The uneven batch: four problems of different shapes and sizes (370k signals in all)
     learned together in one call, K = 10."""
@@ -258,6 +290,7 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-error-driven", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one elementwise FP32 copy of MIB MiB (reads and writes MIB MiB): "
                          "the reference dispatch that scales hardware byte counters")
@@ -355,6 +388,7 @@ def main():
         learned = learned_vs_plain(args, api, oracle, synth)
     mixed = None if args.no_mixed else mixed_workload(api, oracle, synth)
     uneven = None if args.no_uneven else uneven_workload(api, oracle, synth)
+    errdriven = None if args.no_error_driven else error_driven_workload(api, oracle, synth)
 
     symbol = kernel_symbol(w, tuned)
     out = {
@@ -390,6 +424,7 @@ def main():
         "learned_vs_plain": learned,
         "mixed_precision": mixed,
         "uneven_batch": uneven,
+        "error_driven": errdriven,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
