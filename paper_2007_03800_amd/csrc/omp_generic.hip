@@ -245,7 +245,9 @@ template <typename T>
 hipError_t launch_omp_generic(const OmpArgs<T>& a, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
   const size_t lds = omp_generic_lds_bytes(a.m1, a.m2, a.n1, a.n2, a.s, sizeof(T));
-  int64_t grid = a.N < 16384 ? a.N : 16384;
+  // single-wave workgroups, each striding over the signals; 65,536 of them (a few signals each
+  // at 10^5 signals) balance the tail better than fewer, longer ones
+  int64_t grid = a.N < 65536 ? a.N : 65536;
   hipLaunchKernelGGL(omp_generic_kernel<T>, dim3((unsigned)grid), dim3(kWave), lds, st, a);
   return hipGetLastError();
 }
