@@ -37,13 +37,41 @@ def omp_flops_per_signal(m1, m2, n1, n2, s):
 
 
 def sums_flops_per_signal(m1, m2, n1, n2, s):
-    """Algorithmic FLOPs of one signal's contribution to the TMOD sums that the
-    sparse-coding launch accumulates in its epilogue (Corollary 1, dense products,
-    symmetric A counted in full), averaged over the D1-side and D2-side launches:
-    T = X D2^T from s nonzeros, A += T T^T, B += Y T^T (and the mirror for D2)."""
+    """Algorithmic FLOPs of one signal's contribution to one side's TMOD sums, using the
+    sparsity of X_k: B += Y_k T_k^T touches only the s used atom columns (2 s m1 m2) and
+    A += X_k G X_k^T has s^2 nonzero products (2 s^2)."""
+    return 2 * s * m1 * m2 + 2 * s * s
+
+
+def sums_flops_executed_per_signal(m1, m2, n1, n2, s):
+    """FLOPs the sums epilogue actually executes per signal (dense T_k = X_k D2^T and dense
+    products on the matrix cores, symmetric A in full), averaged over the two sides."""
     side1 = 2 * s * m2 + 2 * n1 * n1 * m2 + 2 * m1 * n1 * m2
     side2 = 2 * s * m1 + 2 * n2 * n2 * m1 + 2 * m2 * n2 * m1
     return (side1 + side2) / 2
+
+
+def median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def timed_runs(run, reps):
+    """reps runs of run(), each bracketed by torch.cuda.synchronize() and by HIP events on the
+    current stream; returns (median wall seconds, median event seconds, all wall seconds)."""
+    import torch
+    walls, evs = [], []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        evs.append(e0.elapsed_time(e1) * 1e-3)
+    return median(walls), median(evs), walls
 
 
 def omp_bytes_per_signal(m1, m2, s, elem):
@@ -117,13 +145,14 @@ def learned_vs_plain(args, api, oracle, synth):
     Ysub = synth.signals(w, ntr, ntr + nsub)
     for name, kw in (("plain", {}), ("learned", {"proposer": net, "tau": tau})):
         pr = api.Problem(Yev, D1.clone(), D2.clone(), w.s)
-        api.learn(pr, 1, **kw)  # warm-up
-        pr = api.Problem(Yev, D1.clone(), D2.clone(), w.s)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        api.learn(pr, K, **kw)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+
+        def run():
+            pr.D1.copy_(D1)
+            pr.D2.copy_(D2)
+            api.learn(pr, K, **kw)
+
+        run()  # warm-up (captures the learning graph)
+        dt, _, _ = timed_runs(run, 3)
         s_o, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
         r_g = pr.res2[:nsub].double().cpu().numpy()
         out[name + "_value"] = nev * K / dt
@@ -156,18 +185,27 @@ def device_signals(synth, w, dtype, k0=0, k1=None, chunk=100_000):
     return Y
 
 
-def timed_learn(api, fresh, K):
-    """Autotune, one warm-up iteration, then K graph-replayed iterations of Algorithm 1 from
-    fresh problems; returns (problems, trace, seconds)."""
+def timed_learn(api, fresh, K, reps=3):
+    """Autotune, one untimed run of K iterations (it also captures the learning graph), then the
+    median of reps timed runs of K graph-replayed iterations of Algorithm 1, each from the initial
+    dictionaries on the same buffers; returns (problems, trace, seconds)."""
     import torch
     api.autotune(fresh(), reps=3)
-    api.learn(fresh(), 1)
     probs = fresh()
+    plist = probs if isinstance(probs, list) else [probs]
+    init = [(p.D1.clone(), p.D2.clone()) for p in plist]
+    traces = []
+
+    def run():
+        for p, (a, b) in zip(plist, init):
+            p.D1.copy_(a)
+            p.D2.copy_(b)
+        traces.append(api.learn(probs, K))
+
+    run()
+    dt, _, _ = timed_runs(run, reps)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    trace = api.learn(probs, K)
-    torch.cuda.synchronize()
-    return probs, trace, time.perf_counter() - t0
+    return probs, traces[-1], dt
 
 
 def kernel_name(api, w):
@@ -277,6 +315,43 @@ def uneven_workload(api, oracle, synth):
             "ms_per_step": dt / K * 1e3, "problems": per}
 
 
+def cpu_baseline(args, oracle, synth, w, d1, d2):
+    """The FP64 oracle (Algorithm 1, plain C loops) built with -O3 -march=native for this host, timed
+    on a bounded prefix of the same workload: with as many threads as the process may use and with
+    one thread; each one warm-up run and the median of three."""
+    import tempfile
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    p = max(1, min(int(os.environ.get("OMP_NUM_THREADS", cores)), cores))
+    with tempfile.TemporaryDirectory(prefix="sdlref_") as tmp:
+        lib = oracle.build_native(tmp)
+        out = {}
+        for name, threads, ns, K in (("all", p, min(args.cpu_sample, w.N), args.cpu_iters),
+                                     ("single", 1, min(args.cpu_sample_1t, w.N), args.cpu_iters_1t)):
+            Yc = synth.signals(w, 0, ns)
+            times = []
+            for r in range(4):  # one warm-up, then three timed
+                t0 = time.perf_counter()
+                oracle.learn(Yc, d1, d2, w.s, K, p=threads, lib=lib)
+                if r:
+                    times.append(time.perf_counter() - t0)
+            # K iterations (+ the final sparse coding the call includes) over ns signals
+            out[name] = {"value": ns * K / median(times), "threads": threads, "signals": ns, "iterations": K,
+                         "seconds_median": median(times)}
+    a = out["all"]
+    return {"value": a["value"], "unit": "signals/s per iteration", "cores": a["threads"], "kind": "oracle",
+            "sample": "first %d signals of the workload, %d Algorithm-1 iterations plus the final 2D-OMP, FP64 "
+                      "oracle built -O3 -march=native, %d threads, median of 3 after a warm-up"
+                      % (a["signals"], a["iterations"], a["threads"]),
+            "single_thread": {"value": out["single"]["value"], "unit": "signals/s per iteration", "cores": 1,
+                              "sample": "first %d signals, %d iterations plus the final 2D-OMP, 1 thread, median "
+                                        "of 3 after a warm-up" % (out["single"]["signals"],
+                                                                   out["single"]["iterations"])},
+            "seconds": {k: v["seconds_median"] for k, v in out.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,8 +359,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp32_8x8_n16_s8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--runs", type=int, default=5, help="timed runs of K steps; the median is reported")
     ap.add_argument("--cpu-sample", type=int, default=100000)
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-sample-1t", type=int, default=10000)
+    ap.add_argument("--cpu-iters-1t", type=int, default=5)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-mixed", action="store_true")
@@ -333,13 +411,19 @@ def main():
     if args.warmup > 0:
         api.learn(pr, args.warmup)
     torch.cuda.synchronize()
-    pr = fresh()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    trace = api.learn(pr, args.steps)[0]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+    # the timed problem keeps its buffers across runs (the library replays the learning graph it
+    # captured for them); each run starts again from the initial dictionaries
+    D1_0, D2_0 = pr.D1.clone(), pr.D2.clone()
+    traces = []
+
+    def run():
+        pr.D1.copy_(D1_0)
+        pr.D2.copy_(D2_0)
+        traces.append(api.learn(pr, args.steps)[0])
+
+    run()  # captures the graph for K = steps (not timed)
+    elapsed, elapsed_ev, all_runs = timed_runs(run, args.runs)
+    trace = traces[-1]
     value = w.N * args.steps / elapsed
 
     # dominant kernel timing: same workload, eager launches bracketed by HIP events on their stream
@@ -351,6 +435,8 @@ def main():
     # the launch codes every signal and accumulates its share of the next update's sums
     flops = (omp_flops_per_signal(w.m1, w.m2, w.n1, w.n2, w.s) +
              sums_flops_per_signal(w.m1, w.m2, w.n1, w.n2, w.s)) * w.N
+    flops_exec = (omp_flops_per_signal(w.m1, w.m2, w.n1, w.n2, w.s) +
+                  sums_flops_executed_per_signal(w.m1, w.m2, w.n1, w.n2, w.s)) * w.N
     achieved_tflops = flops / (omp_ms * 1e-3) / 1e12
     per_class = {k: round(v / sd["kernel_launches"][k], 4) for k, v in sd["kernel_ms"].items()}
 
@@ -364,18 +450,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        p = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        p = max(1, min(p, os.cpu_count() or 1))
-        ns = min(args.cpu_sample, w.N)
-        Yc = synth.signals(w, 0, ns)
-        tc0 = time.perf_counter()
-        oracle.learn(Yc, d1, d2, w.s, args.cpu_iters, p=p)
-        tc1 = time.perf_counter()
-        # K iterations (+ the final sparse coding the call includes) over ns signals
-        cpu = {"value": ns * args.cpu_iters / (tc1 - tc0), "unit": "signals/s per iteration", "cores": p,
-               "kind": "oracle", "seconds": tc1 - tc0,
-               "sample": "first %d signals of the workload, %d Algorithm-1 iterations plus the final 2D-OMP, "
-                         "FP64 oracle, %d threads" % (ns, args.cpu_iters, p)}
+        cpu = cpu_baseline(args, oracle, synth, w, d1, d2)
 
     # measured ceilings of this device (copy kernel, FMA and MFMA chains)
     measured = {"hbm_copy_gbs": api.probe_hbm_copy(1 << 30, reps=5)}
@@ -399,6 +474,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3,
+        "timing": {"runs": args.runs, "statistic": "median", "wall_ms_per_step_runs":
+                   [round(t / args.steps * 1e3, 5) for t in all_runs],
+                   "event_ms_per_step": elapsed_ev / args.steps * 1e3},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -414,7 +492,9 @@ def main():
                      "peak": FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6, "unit": "TFLOP/s",
                      "frac": achieved_tflops / (FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6),
                      "traffic": measured_traffic(w, symbol), "traffic_unit": "bytes/launch",
-                     "avg_ms": omp_ms, "flops_per_launch": flops,
+                     "avg_ms": omp_ms, "flops_per_launch": flops, "flops_executed_per_launch": flops_exec,
+                     "frac_executed": flops_exec / (omp_ms * 1e-3) / 1e12 /
+                     (FP32_VECTOR_PEAK_TFLOPS if elem == 4 else 78.6),
                      "peak_measured": peak_meas, "frac_measured": achieved_tflops / peak_meas},
         "measured_peaks": measured,
         "kernel_avg_ms": per_class,

@@ -5,7 +5,7 @@
  * approximated as Y_k ~ D1 X_k D2^T with s-sparse X_k (n1 x n2) and unit-norm
  * atoms (eq. (1)).  Sparse coding is 2D-OMP (Sec. III, step 1); the dictionary
  * updates are the least-squares solutions of Corollary 1 (D1) and
- * Proposition 1 (D2) followed by normalisation; learning iterates them as in
+ * Result 1 (D2) followed by normalisation; learning iterates them as in
  * Algorithm 1.
  *
  * Layout: every matrix is column-major (the paper's vec, Sec. I).
@@ -15,10 +15,8 @@
  *   supp[k*s + t]: t-th atom chosen for signal k (selection order), -1 = unused slot
  *   coef[k*s + t]: its coefficient, 0 in unused slots
  * Element type of Y, coef and res2: double for SDL_FP64, float for SDL_FP32; for
- * SDL_BF16 (mixed precision) Y holds bfloat16 values (16-bit patterns equal to the upper
- * half of the FP32 encoding) and coef/res2 are float: signals are widened to FP32
- * exactly where they are loaded, the sparse coding and the sums run in FP32, the
- * dictionary solves in FP64 as for the other precisions.
+ * SDL_BF16 and SDL_MIXED_BF16 Y holds bfloat16 values (16-bit patterns equal to the upper
+ * half of the FP32 encoding) and coef/res2 are float.
  *
  * Pointers: every array pointer is a DEVICE pointer (HIP global memory) unless
  * marked "host".  The caller allocates and owns all of them and keeps them alive
@@ -43,9 +41,16 @@
 extern "C" {
 #endif
 
-#define SDL_ABI_VERSION 4
+#define SDL_ABI_VERSION 5
 
-typedef enum { SDL_FP64 = 0, SDL_FP32 = 1, SDL_BF16 = 2 } sdl_prec;
+/* SDL_FP64, SDL_FP32: the signals and every step in that precision (dictionary solves in FP64).
+ * SDL_BF16: bfloat16 signals widened to FP32 where loaded; every step as SDL_FP32.
+ * SDL_MIXED_BF16: bfloat16 signals; the correlations D1^T R_k D2 of every 2D-OMP step are
+ *   contractions on the BF16 matrix cores with FP32 accumulation, every atom whose BF16
+ *   |correlation| lies within tie_band (relative) of the largest is re-scored in FP32 before
+ *   the pick, the residual, the chosen atom's correlation and the Cholesky factor are FP32, and
+ *   the dictionary sums and solves are as for SDL_BF16.  Shapes: see sdl_mixed_supported. */
+typedef enum { SDL_FP64 = 0, SDL_FP32 = 1, SDL_BF16 = 2, SDL_MIXED_BF16 = 3 } sdl_prec;
 
 enum {
   SDL_OK = 0,
@@ -118,6 +123,23 @@ typedef struct sdl_options {
                                eps = 1.15 sigma sqrt(m1 m2), err2 = eps^2, s = m1 m2 / 2).  0 = off
                                (default); negative or NaN: SDL_E_INVAL.  Runs on the generic kernel:
                                kernel 2 or 3, or a learned proposal, with err2 > 0 is SDL_E_UNSUPPORTED */
+  double tie_band;          /* SDL_MIXED_BF16: atoms whose BF16 |correlation| is at least (1 - tie_band) times
+                               the largest are re-scored in FP32 and the pick is the largest FP32 |correlation|
+                               among them (ties: smallest atom).  Default 2^-6; must be in [0, 0.5) */
+  double fallback_margin;   /* learned proposal: sdl_proposer_calibrate counts a calibration signal as a
+                               violation when its proposal's ||r||^2 exceeds fallback_margin times plain
+                               2D-OMP's (default 1.01: "more than 1% worse"); must be >= 1 */
+  int32_t deterministic;    /* 1 (default): results are bitwise reproducible run to run for the same inputs,
+                               launch configuration and device.  Every path of this library already is (the
+                               sums use fixed-order FP64 reductions and no floating-point atomics), so 0 is
+                               accepted and gives the same results */
+  int32_t reserved0;        /* must be 0 */
+  void* workspace;          /* device memory the call uses instead of the library's own workspace (NULL: the
+                               library allocates and keeps one per device and stream).  At least
+                               sdl_workspace_bytes() bytes, 256-byte aligned, owned by the caller, not used by
+                               calls that may overlap in time; its contents need not be preserved between calls.
+                               Too small: SDL_E_NOMEM before any work is queued */
+  size_t workspace_bytes;   /* size of workspace in bytes */
 } sdl_options;
 
 /* Fill *o with the defaults above (prec = SDL_FP64).  Passing NULL options to the
@@ -132,7 +154,7 @@ void sdl_default_options(sdl_options* o);
 int sdl_sparse_code(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream);
 
 /* TMOD dictionary update(s) from the codes in supp/coef (Algorithm 1 steps 2 and
- * 4; Corollary 1 for D1, Proposition 1 for D2).  sides: 1 = D1, 2 = D2, 3 = D1
+ * 4; Corollary 1 for D1, Result 1 for D2).  sides: 1 = D1, 2 = D2, 3 = D1
  * then D2.  For each side: partial sums over all signals, FP64 solve on the
  * atoms used by some code, unit-norm normalisation, and rescaling of coef so
  * every product D1 X_k D2^T is unchanged.  Synchronises `stream` before
@@ -146,6 +168,32 @@ int sdl_tmod_update(sdl_problem* p, int32_t nprob, uint32_t sides, const sdl_opt
  * (t = K: the final one).  D1, D2 are updated in place.  Synchronises. */
 int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, const sdl_options* o,
               void* stream);
+
+/* The work of one node of Algorithm 1 in its step 1 (side 1) or step 3 (side 2): 2D-OMP of the
+ * problem's signals as sdl_sparse_code does it (supp, coef and res2 written), then the sums that
+ * node sends to the master, formed from the new codes:
+ *   side 1 (Corollary 1):  T_k = X_k D2^T,  A = sum_k T_k T_k^T (n1 x n1),  B = sum_k Y_k T_k^T (m1 x n1)
+ *   side 2 (Result 1):     Z_k = D1 X_k,    A = sum_k Z_k^T Z_k (n2 x n2),  B = sum_k Y_k^T Z_k (m2 x n2)
+ * and the total squared residual sum_k res2_k.  sums (device, FP64, na*na + mr*na + 1 doubles with
+ * na = n1, mr = m1 for side 1 and na = n2, mr = m2 for side 2): A column-major at sums[0], B
+ * column-major at sums[na*na], the residual total last.  The sums are the ones sdl_learn solves:
+ * on the register-resident FP32/BF16 kernels they are accumulated in the sparse-coding launch
+ * itself (FP32 products, FP64 across workgroups), otherwise by the standalone sums kernel after
+ * it; every reduction has a fixed order.  One problem; res2 must not be NULL.  On one GPU this is
+ * what each GPU of a multi-GPU run would contribute to an all-reduce before the solve.
+ * Asynchronous on `stream`. */
+int sdl_sparse_code_sums(const sdl_problem* p, int32_t side, double* sums, const sdl_options* o, void* stream);
+
+/* Device workspace bytes a call of kind `call` (0 sdl_sparse_code, 1 sdl_tmod_update,
+ * 2 sdl_learn with K iterations, 3 sdl_sparse_code_sums) on these problems with these options
+ * needs when sdl_options.workspace is given (the size the library would allocate itself).
+ * Host only: queues no device work. */
+int sdl_workspace_bytes(const sdl_problem* p, int32_t nprob, int32_t call, int32_t K, const sdl_options* o,
+                        size_t* bytes);
+
+/* 1 if SDL_MIXED_BF16 has a kernel for this shape (signal rows and columns and atom counts
+ * multiples of 4 within the compiled set), else 0. */
+int sdl_mixed_supported(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s);
 
 /* Autotuner (no counterpart in the paper; a property of this GPU implementation):
  * for every FP32 problem whose shape has register-resident kernel variants
@@ -221,10 +269,18 @@ int sdl_learned_sparse_code(sdl_proposer* p, const sdl_problem* prob, int32_t np
                             const sdl_options* o, void* stream);
 /* Choose tau on a calibration problem: run the proposal (accepting everything) and plain
  * 2D-OMP, sort signals by ||r_prop||^2/||Y||^2 and return the largest threshold such that at
- * most `violation` of the accepted signals have ||r_prop||^2 > 1.01 * ||r_omp||^2.  The
- * problem's codes are overwritten. */
-int sdl_proposer_calibrate(sdl_proposer* p, const sdl_problem* prob, double violation, double* tau_out,
-                           void* stream);
+ * most `violation` of the accepted signals have ||r_prop||^2 > m * ||r_omp||^2, with
+ * m = o->fallback_margin (default 1.01; o may be NULL).  The problem's codes are overwritten. */
+int sdl_proposer_calibrate(sdl_proposer* p, const sdl_problem* prob, double violation, const sdl_options* o,
+                           double* tau_out, void* stream);
+
+/* Save the network to a file: a fixed header (magic "SDLPROP1", m1, m2, n1, n2, hidden, fp32_check as
+ * int32, the parameter count as int64) followed by the FP32 master weights in the flat layout above,
+ * little-endian.  The Adam state is not saved.  SDL_E_INVAL for NULL arguments or an unwritable path. */
+int sdl_proposer_save(const sdl_proposer* p, const char* path);
+/* Create a network from a file written by sdl_proposer_save (weights restored, Adam state reset).
+ * SDL_E_INVAL if the file cannot be read or is not such a file. */
+int sdl_proposer_load(const char* path, sdl_proposer** out);
 
 /* Measurement aids (no counterpart in the paper): achievable ceilings of the current
  * device, for quoting kernel fractions against measured as well as published peaks.
@@ -233,7 +289,8 @@ int sdl_proposer_calibrate(sdl_proposer* p, const sdl_problem* prob, double viol
  * grid-stride kernel and stores the best rate, read plus write bytes, in *gbs (1e9 B/s).
  * sdl_probe_peak runs independent arithmetic chains on every SIMD and stores the best of
  * reps launches in *tflops: kind 0 = FP32 FMA on the vector ALUs (unpacked), 1 = FP32
- * MFMA 16x16x4, 2 = FP32 MFMA 4x4x1 (16 blocks), 3 = FP64 FMA.  sink: device, >= 8 bytes,
+ * MFMA 16x16x4, 2 = FP32 MFMA 4x4x1 (16 blocks), 3 = FP64 FMA, 4 = BF16 MFMA 4x4x4 (16 blocks),
+ * 5 = BF16 MFMA 16x16x16, 6 = BF16 MFMA 16x16x32 (FP32 accumulation for 4-6).  sink: device, >= 8 bytes,
  * written only if a chain reaches a value it cannot reach.  Both synchronise the stream;
  * SDL_E_INVAL for NULL pointers, bytes < 16, reps < 1 or an unknown kind. */
 int sdl_probe_hbm_copy(void* dst, const void* src, size_t bytes, int32_t reps, double* gbs, void* stream);

@@ -30,25 +30,39 @@ STOP_REL = 1e-14
 DEP_EPS = 1e-10
 
 
+def _compile(out: str, march: str) -> str:
+    tmp = out + ".tmp%d" % os.getpid()
+    # ISO C mode: gcc contracts no a*b+c into FMA (-ffp-contract=off), so the results do not
+    # depend on the target's instruction set
+    subprocess.check_call(["gcc", "-O3", "-march=" + march, "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                           "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (portable flags, OpenMP for the shard split)."""
+    """Compile the oracle with gcc: -O3 for the x86-64-v3 level (AVX2 and FMA, which every host
+    this runs on has), OpenMP for the shard split."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+        _compile(_LIB, "x86-64-v3")
     return _LIB
 
 
-_lib = None
+def build_native(directory: str) -> str:
+    """The same source compiled with -O3 -march=native for the host it runs on, into
+    ``directory`` (for timing the oracle on that host); returns the library path."""
+    return _compile(os.path.join(directory, "libsdlref_native.so"), "native")
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+_libs = {}
+
+
+def _load(path=None):
+    path = path or _LIB
+    if path not in _libs:
+        if path == _LIB and not os.path.exists(_LIB):
             build()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         i32, i64, dp, ip, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double
         lib.sdlref_omp.argtypes = [i32, i32, i32, i32, i32, i32, i64, dp, dp, dp, ip, dp, dp, f64, f64, i32]
         lib.sdlref_omp_err.argtypes = [i32, i32, i32, i32, i32, i32, i64, dp, dp, dp, ip, dp, dp, f64, f64, f64, i32]
@@ -58,8 +72,8 @@ def _load():
                                      f64, f64, i32]
         for f in (lib.sdlref_omp, lib.sdlref_omp_err, lib.sdlref_tmod_sums, lib.sdlref_tmod_update, lib.sdlref_learn):
             f.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return _libs[path]
 
 
 class OracleError(RuntimeError):
@@ -129,8 +143,9 @@ def tmod_update(side, Y, D1, D2, supp, coef, p=1):
     return D1c.T.copy(), D2c.T.copy(), c, w
 
 
-def learn(Y, D1, D2, s, K, schedule=0, p=1, stop_rel=STOP_REL, dep_eps=DEP_EPS, allow_singular=False):
-    """Algorithm 1 for K iterations plus a final OMP.
+def learn(Y, D1, D2, s, K, schedule=0, p=1, stop_rel=STOP_REL, dep_eps=DEP_EPS, allow_singular=False, lib=None):
+    """Algorithm 1 for K iterations plus a final OMP.  lib: path of another build of the same
+    source (build_native), else the default one.
 
     Returns dict(D1, D2, supp, coef, res2, rmse, status)."""
     Y = np.asarray(Y, np.float64)
@@ -141,7 +156,7 @@ def learn(Y, D1, D2, s, K, schedule=0, p=1, stop_rel=STOP_REL, dep_eps=DEP_EPS, 
     coef = np.empty((N, s), np.float64)
     res2 = np.empty(N, np.float64)
     rmse = np.empty(K + 1, np.float64)
-    st = _load().sdlref_learn(m1, m2, n1, n2, s, N, K, schedule, _ptr(_cm(Y)), _ptr(D1c), _ptr(D2c),
+    st = _load(lib).sdlref_learn(m1, m2, n1, n2, s, N, K, schedule, _ptr(_cm(Y)), _ptr(D1c), _ptr(D2c),
                               _ptr(supp), _ptr(coef), _ptr(res2), _ptr(rmse), stop_rel, dep_eps, p)
     if st != 0 and not (allow_singular and st == -5):
         raise OracleError(st)

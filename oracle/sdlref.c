@@ -7,7 +7,7 @@
  *     unit-norm atoms (eq. (1));
  *   - sparse coding: 2D-OMP (Sec. III step 1, Sec. II), which equals OMP on
  *     the Kronecker dictionary D2 (x) D1 under column-major vec (Sec. I);
- *   - dictionary updates: Proposition 1 (D2) and Corollary 1 (D1), followed by
+ *   - dictionary updates: Result 1 (D2) and Corollary 1 (D1), followed by
  *     column normalisation with the compensating rescaling of X;
  *   - iteration: Algorithm 1 (OMP, D1 update, OMP, D2 update).
  *
@@ -480,7 +480,7 @@ int sdlref_tmod_update(int side, int m1, int m2, int n1, int n2, int s, int64_t 
   for (int i = 0; i < na; ++i)
     if (A[i + na * i] > 0.0) U[nu++] = i;
 
-  /* Corollary 1 / Proposition 1: D* (mb x na) solves D* A = B on the used set,
+  /* Corollary 1 / Result 1: D* (mb x na) solves D* A = B on the used set,
    * i.e. A_UU (D*_U)^T = (B_U)^T with A_UU symmetric positive definite. */
   for (int k = 0; k < nu; ++k)
     for (int l = 0; l < nu; ++l) Lm[k * nu + l] = A[U[k] + na * U[l]];
@@ -492,7 +492,7 @@ int sdlref_tmod_update(int side, int m1, int m2, int n1, int n2, int s, int64_t 
     chol_solve(Lm, nu, rhs);
     for (int k = 0; k < nu; ++k) Dn[pp + mb * U[k]] = rhs[k];
   }
-  /* normalisation W (Proposition 1 / Corollary 1): unit-norm columns */
+  /* normalisation W (Result 1 / Corollary 1): unit-norm columns */
   for (int i = 0; i < na; ++i) w[i] = 1.0;
   for (int k = 0; k < nu; ++k) {
     int i = U[k];

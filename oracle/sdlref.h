@@ -39,7 +39,7 @@ int sdlref_omp_err(int mode, int m1, int m2, int n1, int n2, int s, int64_t N,
 /* Dense partial sums of one TMOD half-step, by their definitions.
  * side 1 (Corollary 1): T_k = X_k D2^T;  A = sum T_k T_k^T (n1 x n1),
  *                       B = sum Y_k T_k^T (m1 x n1).
- * side 2 (Proposition 1): Z_k = D1 X_k; A = sum Z_k^T Z_k (n2 x n2),
+ * side 2 (Result 1): Z_k = D1 X_k; A = sum Z_k^T Z_k (n2 x n2),
  *                       B = sum Y_k^T Z_k (m2 x n2).
  * A, B column-major.  Sums are taken per shard in signal order, then over
  * shards in shard order. */

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsdl.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "sdl.h")
 
-SDL_FP64, SDL_FP32, SDL_BF16 = 0, 1, 2
+SDL_FP64, SDL_FP32, SDL_BF16, SDL_MIXED_BF16 = 0, 1, 2, 3
 STATUS = {0: "SDL_OK", -1: "SDL_E_INVAL", -2: "SDL_E_SHAPE", -3: "SDL_E_DEVICE", -4: "SDL_E_NOMEM",
           -5: "SDL_E_SINGULAR", -6: "SDL_E_NONFINITE", -7: "SDL_E_UNSUPPORTED"}
 KERNEL_CLASSES = ["sparse_code", "tmod_sums", "reduce", "solve", "prep", "rmse", "rescale", "spare"]
@@ -42,7 +42,9 @@ class Options(ctypes.Structure):
                 ("check_finite", ctypes.c_int32), ("timing", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("stop_rel", ctypes.c_double), ("dep_eps", ctypes.c_double), ("pivot_fp64", ctypes.c_double),
                 ("stats", ctypes.POINTER(Stats)), ("proposer", ctypes.c_void_p), ("tau", ctypes.c_double),
-                ("err2", ctypes.c_double)]
+                ("err2", ctypes.c_double), ("tie_band", ctypes.c_double), ("fallback_margin", ctypes.c_double),
+                ("deterministic", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 class SdlError(RuntimeError):
@@ -91,7 +93,16 @@ def lib():
         L.sdl_proposer_train.argtypes = [vp, vp, vp, i32, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, vp, vp]
         L.sdl_proposer_logits.argtypes = [vp, vp, i64, vp, vp]
         L.sdl_learned_sparse_code.argtypes = [vp, P, i32, vp, ctypes.POINTER(Options), vp]
-        L.sdl_proposer_calibrate.argtypes = [vp, P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+        L.sdl_proposer_calibrate.argtypes = [vp, P, ctypes.c_double, ctypes.POINTER(Options),
+                                             ctypes.POINTER(ctypes.c_double), vp]
+        L.sdl_proposer_save.argtypes = [vp, ctypes.c_char_p]
+        L.sdl_proposer_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.sdl_sparse_code_sums.argtypes = [P, i32, vp, ctypes.POINTER(Options), vp]
+        L.sdl_workspace_bytes.argtypes = [P, i32, i32, i32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]
+        L.sdl_mixed_supported.argtypes = [i32] * 5
+        for f in (L.sdl_proposer_save, L.sdl_proposer_load, L.sdl_sparse_code_sums, L.sdl_workspace_bytes,
+                  L.sdl_mixed_supported):
+            f.restype = ctypes.c_int
         L.sdl_probe_hbm_copy.argtypes = [vp, vp, ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_double), vp]
         L.sdl_probe_hbm_copy.restype = ctypes.c_int
         L.sdl_probe_peak.argtypes = [i32, vp, i32, ctypes.POINTER(ctypes.c_double), vp]

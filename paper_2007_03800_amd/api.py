@@ -21,6 +21,8 @@ import torch
 from . import _native
 
 _DT = {torch.float64: _native.SDL_FP64, torch.float32: _native.SDL_FP32, torch.bfloat16: _native.SDL_BF16}
+PRECISIONS = {"fp64": _native.SDL_FP64, "fp32": _native.SDL_FP32, "bf16": _native.SDL_BF16,
+              "mixed_bf16": _native.SDL_MIXED_BF16}
 
 
 class Problem:
@@ -80,11 +82,17 @@ class Problem:
 
 
 def _options(problems, stats=None, **kw):
+    """Options for a call: the precision follows the signals' dtype; ``mixed=True`` asks for
+    SDL_MIXED_BF16 (bfloat16 signals, correlations on the BF16 matrix cores)."""
     o = _native.default_options()
     precs = {pr.prec for pr in problems}
     if len(precs) > 1:
         raise ValueError("all problems of one call share a precision")
     o.prec = precs.pop() if precs else _native.SDL_FP64
+    if kw.pop("mixed", False):
+        if o.prec != _native.SDL_BF16:
+            raise ValueError("mixed=True needs bfloat16 signals")
+        o.prec = _native.SDL_MIXED_BF16
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError("unknown option %r" % k)
@@ -114,6 +122,43 @@ def sparse_code(problems: Problem | Sequence[Problem], stream=None, stats=None, 
     arr = _array(problems)
     _native.check(_native.lib().sdl_sparse_code(arr, len(problems), ctypes.byref(o), _stream(stream)))
     return problems
+
+
+def sparse_code_sums(problem: Problem, side: int, stream=None, stats=None, **opts) -> torch.Tensor:
+    """2D-OMP of the problem's signals plus the reduced sums of one side's dictionary update
+    (Algorithm 1 step 1 or 3): returns a float64 device tensor [A (na*na) | B (mr*na) | sum res2],
+    A and B column-major (asynchronous on the stream)."""
+    na, mr = (problem.n1, problem.m1) if side == 1 else (problem.n2, problem.m2)
+    out = torch.empty(na * na + mr * na + 1, dtype=torch.float64, device=problem.Y.device)
+    o = _options([problem], stats, **opts)
+    arr = _array([problem])
+    _native.check(_native.lib().sdl_sparse_code_sums(arr, side, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o),
+                                                     _stream(stream)))
+    return out
+
+
+def split_sums(sums, side, problem: Problem):
+    """(A, B, sum res2) in math shape from a sparse_code_sums result (host numpy)."""
+    v = sums.cpu().numpy() if isinstance(sums, torch.Tensor) else sums
+    na, mr = (problem.n1, problem.m1) if side == 1 else (problem.n2, problem.m2)
+    A = v[:na * na].reshape(na, na).T
+    B = v[na * na:na * na + mr * na].reshape(na, mr).T
+    return A.copy(), B.copy(), float(v[-1])
+
+
+def workspace_bytes(problems: Problem | Sequence[Problem], call: str = "learn", K: int = 0, **opts) -> int:
+    """Workspace bytes a call needs when the caller supplies it (options ``workspace``)."""
+    problems = [problems] if isinstance(problems, Problem) else list(problems)
+    kinds = {"sparse_code": 0, "tmod_update": 1, "learn": 2, "sparse_code_sums": 3}
+    o = _options(problems, None, **opts)
+    n = ctypes.c_size_t()
+    _native.check(_native.lib().sdl_workspace_bytes(_array(problems), len(problems), kinds[call], K,
+                                                    ctypes.byref(o), ctypes.byref(n)))
+    return n.value
+
+
+def mixed_supported(m1, m2, n1, n2, s) -> bool:
+    return bool(_native.lib().sdl_mixed_supported(m1, m2, n1, n2, s))
 
 
 def tmod_update(problems: Problem | Sequence[Problem], sides: int = 3, stream=None, stats=None, **opts):
@@ -237,12 +282,28 @@ class Proposer:
                                                         ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
-    def calibrate(self, problem: Problem, violation=0.01, stream=None):
+    def calibrate(self, problem: Problem, violation=0.01, fallback_margin=1.01, stream=None):
         tau = ctypes.c_double()
         arr = _array([problem])
-        _native.check(_native.lib().sdl_proposer_calibrate(self._h, arr, violation, ctypes.byref(tau),
-                                                           _stream(stream)))
+        o = _native.default_options()
+        o.prec = _native.SDL_FP32
+        o.fallback_margin = fallback_margin
+        _native.check(_native.lib().sdl_proposer_calibrate(self._h, arr, violation, ctypes.byref(o),
+                                                           ctypes.byref(tau), _stream(stream)))
         return tau.value
+
+    def save(self, path):
+        _native.check(_native.lib().sdl_proposer_save(self._h, str(path).encode()))
+
+    @classmethod
+    def load(cls, path):
+        import struct
+        self = cls.__new__(cls)
+        self._h = ctypes.c_void_p()
+        _native.check(_native.lib().sdl_proposer_load(str(path).encode(), ctypes.byref(self._h)))
+        with open(path, "rb") as f:  # the header's sizes (the library has validated the file)
+            self.m1, self.m2, self.n1, self.n2, self.hidden, _ = struct.unpack("<6i", f.read(32)[8:32])
+        return self
 
 
 def learned_sparse_code(proposer: Proposer, problems, tau: float, accept: torch.Tensor | None = None, stream=None,
@@ -262,7 +323,8 @@ def new_stats() -> _native.Stats:
     return _native.Stats()
 
 
-PROBE_KINDS = {"fp32_fma": 0, "fp32_mfma_16x16x4": 1, "fp32_mfma_4x4x1": 2, "fp64_fma": 3}
+PROBE_KINDS = {"fp32_fma": 0, "fp32_mfma_16x16x4": 1, "fp32_mfma_4x4x1": 2, "fp64_fma": 3,
+               "bf16_mfma_4x4x4": 4, "bf16_mfma_16x16x16": 5, "bf16_mfma_16x16x32": 6}
 
 
 def probe_hbm_copy(nbytes: int = 1 << 30, reps: int = 5, stream=None) -> float:

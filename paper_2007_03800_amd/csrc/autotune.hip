@@ -11,6 +11,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -31,6 +32,9 @@ struct Choice {
 std::mutex g_tune_mu;
 std::map<Key, Choice> g_choice;
 std::map<Key, Choice> g_wave;  // shapes for which the one-wave-per-signal path won (id unused)
+// Bumped whenever a kernel choice changes, so captured graphs that baked in the old choice
+// are not replayed.
+std::atomic<long> g_tune_epoch{0};
 bool g_cache_loaded = false;
 
 int find_variant(int m1, int m2, int n1, int n2, int s, int lr, int lc, int wpe, int mfma) {
@@ -81,6 +85,12 @@ void append_cache(const Key& k, int id, double ms) {
 
 }  // namespace
 
+long tuning_epoch() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_cache_locked();
+  return g_tune_epoch.load();
+}
+
 int omp_fast_choice(int m1, int m2, int n1, int n2, int s) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   load_cache_locked();
@@ -94,6 +104,7 @@ int omp_fast_choice(int m1, int m2, int n1, int n2, int s) {
 void omp_fast_set_choice(int m1, int m2, int n1, int n2, int s, int id) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_choice[Key(m1, m2, n1, n2, s)] = Choice{id, 0.0};
+  ++g_tune_epoch;
 }
 
 bool wave_chosen(int m1, int m2, int n1, int n2, int s) {
@@ -112,6 +123,7 @@ void set_wave_choice(int m1, int m2, int n1, int n2, int s, bool on, double ms) 
   std::lock_guard<std::mutex> lk(g_tune_mu);
   load_cache_locked();
   const Key k(m1, m2, n1, n2, s);
+  ++g_tune_epoch;
   if (!on) {
     g_wave.erase(k);
     return;
@@ -173,6 +185,7 @@ hipError_t autotune_problem(const OmpArgs<float>& a, hipStream_t st, int reps, i
     load_cache_locked();
     const Key k(a.m1, a.m2, a.n1, a.n2, a.s);
     g_choice[k] = Choice{best_id, best};
+    ++g_tune_epoch;
     append_cache(k, best_id, best);
   }
   *chosen = best_id;

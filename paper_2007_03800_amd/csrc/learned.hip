@@ -345,6 +345,58 @@ int sdl_proposer_train(sdl_proposer* P, const float* Y, const int32_t* supp, int
   return SDL_OK;
 }
 
+// File layout: 8-byte magic, six int32 (m1, m2, n1, n2, hidden, fp32_check), int64 parameter
+// count, then the FP32 master weights (host byte order; little-endian on the hosts this runs on).
+static const char kPropMagic[8] = {'S', 'D', 'L', 'P', 'R', 'O', 'P', '1'};
+
+int sdl_proposer_save(const sdl_proposer* P, const char* path) {
+  if (!P || !path) return abi_fail(SDL_E_INVAL, "NULL argument");
+  std::vector<float> h((size_t)P->np);
+  ST(sdl_proposer_get_params(P, h.data()));
+  FILE* f = fopen(path, "wb");
+  if (!f) return abi_fail(SDL_E_INVAL, "cannot open the file for writing");
+  const int32_t dims[6] = {P->m1, P->m2, P->n1, P->n2, P->H, P->fp32};
+  const int64_t np = P->np;
+  bool ok = fwrite(kPropMagic, 1, 8, f) == 8 && fwrite(dims, sizeof(int32_t), 6, f) == 6 &&
+            fwrite(&np, sizeof(int64_t), 1, f) == 1 && fwrite(h.data(), sizeof(float), h.size(), f) == h.size();
+  ok = (fclose(f) == 0) && ok;
+  return ok ? SDL_OK : abi_fail(SDL_E_INVAL, "writing the file failed");
+}
+
+int sdl_proposer_load(const char* path, sdl_proposer** out) {
+  if (!path || !out) return abi_fail(SDL_E_INVAL, "NULL argument");
+  *out = nullptr;
+  FILE* f = fopen(path, "rb");
+  if (!f) return abi_fail(SDL_E_INVAL, "cannot open the file for reading");
+  char magic[8];
+  int32_t dims[6];
+  int64_t np = 0;
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kPropMagic, 8) == 0 &&
+            fread(dims, sizeof(int32_t), 6, f) == 6 && fread(&np, sizeof(int64_t), 1, f) == 1;
+  sdl_proposer* P = nullptr;
+  if (ok && sdl_proposer_create(dims[0], dims[1], dims[2], dims[3], dims[4], dims[5], 0, &P) != SDL_OK) {
+    fclose(f);
+    return SDL_E_INVAL;  // message set by sdl_proposer_create
+  }
+  ok = ok && P->np == np;
+  std::vector<float> h(ok ? (size_t)np : 0);
+  ok = ok && fread(h.data(), sizeof(float), h.size(), f) == h.size();
+  char extra;
+  ok = ok && fread(&extra, 1, 1, f) == 0;  // nothing after the weights
+  fclose(f);
+  if (!ok) {
+    if (P) sdl_proposer_destroy(P);
+    return abi_fail(SDL_E_INVAL, "not a proposer file written by sdl_proposer_save");
+  }
+  const int st = sdl_proposer_set_params(P, h.data());
+  if (st != SDL_OK) {
+    sdl_proposer_destroy(P);
+    return st;
+  }
+  *out = P;
+  return SDL_OK;
+}
+
 int sdl_proposer_logits(sdl_proposer* P, const float* Y, int64_t N, float* logits, void* stream) {
   if (!P || !Y || !logits) return abi_fail(SDL_E_INVAL, "NULL argument");
   if (N < 0) return abi_fail(SDL_E_INVAL, "N < 0");

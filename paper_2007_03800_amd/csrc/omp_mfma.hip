@@ -80,7 +80,7 @@ constexpr int tri(int k, int l) { return k * (k + 1) / 2 + l; }
 __device__ inline unsigned umax3(unsigned a, unsigned b, unsigned c) { return max(max(a, b), c); }
 
 // Epilogue of one group: the group's contribution to the next dictionary update's sums
-// (Corollary 1 for SIDE 1, Proposition 1 for SIDE 2), accumulated on the matrix cores.
+// (Corollary 1 for SIDE 1, Result 1 for SIDE 2), accumulated on the matrix cores.
 // Each signal's T = X D2^T (SIDE 1) or Z^T = (D1 X)^T (SIDE 2) is written column by
 // column into LDS (tc); support elements that share a row are merged in registers in
 // selection order first, so the columns are plain stores with the same sums as

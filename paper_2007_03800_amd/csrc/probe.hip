@@ -12,6 +12,8 @@ namespace sdl {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kProbeThreads = 256;
 constexpr int kChains = 16;
@@ -55,6 +57,36 @@ __global__ void __launch_bounds__(kProbeThreads) mfma_kernel(float* sink, int it
         acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[k], 0, 0, 0);
       else
         acc[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc[k], 0, 0, 0);
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+  if (s == -1.f) sink[0] = s;
+}
+
+// BF16 matrix-core chains, FP32 accumulation.  KIND 0: 4x4x4 (16 blocks), 1: 16x16x16,
+// 2: 16x16x32.  Operands are small nonzero bfloat16 values.
+template <int KIND>
+__global__ void __launch_bounds__(kProbeThreads) mfma_bf16_kernel(float* sink, int iters) {
+  f32x4 acc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const short h = (short)(0x3A80 + (threadIdx.x % 64));  // about 1e-3
+  const s16x4 a4 = {h, h, h, h};
+  bf16x8 a8;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a8[k] = (__bf16)(1e-3f * (float)(threadIdx.x % 64 + k));
+#pragma unroll 4
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (KIND == 0)
+        acc[k] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a4, a4, acc[k], 0, 0, 0);
+      else if (KIND == 1)
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, a4, acc[k], 0, 0, 0);
+      else
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, a8, acc[k], 0, 0, 0);
     }
   }
   float s = 0.f;
@@ -142,6 +174,24 @@ hipError_t probe_peak(int kind, float* sink, int reps, hipStream_t st, double* t
           [&] {
             hipLaunchKernelGGL(fma_kernel<double>, dim3(blocks), dim3(kProbeThreads), 0, st, (double*)sink, iters);
           },
+          reps, st, &ms);
+      break;
+    case 4:
+      flops = 2.0 * 16 * 64 * 4 * iters * waves;  // 16 blocks of 4x4x4
+      e = best_ms(
+          [&] { hipLaunchKernelGGL(mfma_bf16_kernel<0>, dim3(blocks), dim3(kProbeThreads), 0, st, sink, iters); },
+          reps, st, &ms);
+      break;
+    case 5:
+      flops = 2.0 * 16 * 16 * 16 * 4 * iters * waves;
+      e = best_ms(
+          [&] { hipLaunchKernelGGL(mfma_bf16_kernel<1>, dim3(blocks), dim3(kProbeThreads), 0, st, sink, iters); },
+          reps, st, &ms);
+      break;
+    case 6:
+      flops = 2.0 * 16 * 16 * 32 * 4 * iters * waves;
+      e = best_ms(
+          [&] { hipLaunchKernelGGL(mfma_bf16_kernel<2>, dim3(blocks), dim3(kProbeThreads), 0, st, sink, iters); },
           reps, st, &ms);
       break;
     default:

@@ -55,6 +55,10 @@ struct Ctx {
   std::vector<hipStream_t> branch;
   std::vector<hipEvent_t> branch_join;
   hipEvent_t fork = nullptr;
+  // the last instantiated learning graph and what it was captured for (see graph_key)
+  std::vector<unsigned char> gkey;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
 
 // Problems of one sdl_learn call run as parallel branches of the captured graph (at
@@ -121,6 +125,12 @@ struct Bump {
   }
 };
 
+#define SDL_TRY_WS(expr)         \
+  do {                           \
+    int s_ = (expr);             \
+    if (s_ != SDL_OK) return s_; \
+  } while (0)
+
 // ------------------------------------------------------------------ options / validation
 
 struct Opt {
@@ -130,6 +140,10 @@ struct Opt {
   sdl_proposer* proposer;
   double tau;
   double err2;
+  double tie_band, fallback_margin;
+  int deterministic, reserved0;
+  void* workspace;
+  size_t workspace_bytes;
 };
 
 Opt resolve(const sdl_options* o) {
@@ -150,17 +164,42 @@ Opt resolve(const sdl_options* o) {
   r.proposer = o->proposer;
   r.tau = o->tau;
   r.err2 = o->err2;
+  r.tie_band = o->tie_band;
+  r.fallback_margin = o->fallback_margin;
+  r.deterministic = o->deterministic;
+  r.reserved0 = o->reserved0;
+  r.workspace = o->workspace;
+  r.workspace_bytes = o->workspace_bytes;
   return r;
+}
+
+// Workspace of one call: the caller's (sdl_options.workspace) or the context's own, grown on demand.
+int acquire_ws(Ctx* c, const Opt& o, size_t bytes, hipStream_t st, void** base) {
+  if (o.workspace) {
+    if ((uintptr_t)o.workspace % 256 != 0) return fail(SDL_E_INVAL, "workspace must be 256-byte aligned");
+    if (o.workspace_bytes < bytes)
+      return fail(SDL_E_NOMEM, "workspace of %zu bytes given, %zu needed", o.workspace_bytes, bytes);
+    *base = o.workspace;
+    return SDL_OK;
+  }
+  SDL_TRY_WS(ensure_ws(c, bytes, st));
+  *base = c->ws;
+  return SDL_OK;
 }
 
 int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_in) {
   if (nprob < 0) return fail(SDL_E_INVAL, "nprob = %d < 0", nprob);
   if (nprob > 0 && !p) return fail(SDL_E_INVAL, "problem array is NULL");
-  if (o.prec != SDL_FP64 && o.prec != SDL_FP32 && o.prec != SDL_BF16)
+  if (o.prec != SDL_FP64 && o.prec != SDL_FP32 && o.prec != SDL_BF16 && o.prec != SDL_MIXED_BF16)
     return fail(SDL_E_INVAL, "prec = %d is not an sdl_prec", o.prec);
   if (o.schedule != 0 && o.schedule != 1) return fail(SDL_E_INVAL, "schedule = %d (0 or 1)", o.schedule);
   if (o.kernel < 0 || o.kernel > 3) return fail(SDL_E_INVAL, "kernel = %d (0..3)", o.kernel);
   if (!(o.err2 >= 0.0)) return fail(SDL_E_INVAL, "err2 must be >= 0 (0: off)");
+  if (!(o.tie_band >= 0.0 && o.tie_band < 0.5)) return fail(SDL_E_INVAL, "tie_band must be in [0, 0.5)");
+  if (!(o.fallback_margin >= 1.0)) return fail(SDL_E_INVAL, "fallback_margin must be >= 1");
+  if (o.deterministic != 0 && o.deterministic != 1) return fail(SDL_E_INVAL, "deterministic must be 0 or 1");
+  if (o.reserved0 != 0) return fail(SDL_E_INVAL, "reserved0 must be 0");
+  if (o.workspace && o.workspace_bytes == 0) return fail(SDL_E_INVAL, "workspace given with workspace_bytes = 0");
   if (o.err2 > 0.0 && (o.kernel == 2 || o.kernel == 3))
     return fail(SDL_E_UNSUPPORTED, "the error-driven stop runs on the generic kernel (kernel 0 or 1)");
   const size_t elem = o.prec == SDL_FP64 ? 8 : 4;
@@ -180,6 +219,11 @@ int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_
     if (!r.D1 || !r.D2) return fail(SDL_E_INVAL, "problem %d: D1/D2 is NULL", q);
     if (r.N > 0 && (!r.Y || !r.supp || !r.coef)) return fail(SDL_E_INVAL, "problem %d: Y/supp/coef is NULL", q);
     (void)need_codes_in;
+    if (o.prec == SDL_MIXED_BF16 && !omp_mixed_supported(r.m1, r.m2, r.n1, r.n2, r.s))
+      return fail(SDL_E_UNSUPPORTED, "problem %d: no SDL_MIXED_BF16 kernel for m=%dx%d n=%dx%d s=%d", q, r.m1, r.m2,
+                  r.n1, r.n2, r.s);
+    if (o.prec == SDL_MIXED_BF16 && (o.err2 > 0.0 || o.proposer))
+      return fail(SDL_E_UNSUPPORTED, "SDL_MIXED_BF16 runs plain 2D-OMP (no error-driven stop, no proposer)");
     if (omp_generic_lds_bytes(r.m1, r.m2, r.n1, r.n2, r.s, elem) > 160 * 1024)
       return fail(SDL_E_UNSUPPORTED, "problem %d: working set of one signal exceeds the 160 KiB LDS", q);
   }
@@ -208,7 +252,7 @@ struct Plan {
   int* status;
   unsigned long long* counters;
   int* iter;     // per-problem RMSE counters
-  bool ybf16 = false;  // signals are bfloat16 (SDL_BF16)
+  bool ybf16 = false;  // signals are bfloat16 (SDL_BF16, SDL_MIXED_BF16)
   double* trace; // device trace
   size_t bytes;
 };
@@ -245,6 +289,17 @@ void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Pla
     x.rpart = b.take<double>((size_t)x.rblk);
   }
   pl->bytes = b.off + 256;
+}
+
+// A caller-supplied workspace is checked against the call's layout before any device work.
+int check_workspace(const sdl_problem* p, int nprob, int K, const Opt& o) {
+  if (!o.workspace) return SDL_OK;
+  Plan pl;
+  layout(p, nprob, o.prec == SDL_FP64 ? 8 : 4, K, nullptr, &pl);
+  if ((uintptr_t)o.workspace % 256 != 0) return fail(SDL_E_INVAL, "workspace must be 256-byte aligned");
+  if (o.workspace_bytes < pl.bytes)
+    return fail(SDL_E_NOMEM, "workspace of %zu bytes given, %zu needed", o.workspace_bytes, pl.bytes);
+  return SDL_OK;
 }
 
 // ------------------------------------------------------------------ launch helpers
@@ -304,6 +359,7 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
   a.dep_eps = o.dep_eps;
   a.pivot_fp64 = o.pivot_fp64;
   a.err2 = o.err2;
+  a.tie_band = o.tie_band;
   a.counters = pl.counters;
   a.sums_side = 0;
   a.sums_part = nullptr;
@@ -314,6 +370,7 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
 
 template <typename T>
 bool use_fast(const sdl_problem& r, const Opt& o) {
+  if (o.prec == SDL_MIXED_BF16) return false;
   if (!omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s) || o.err2 > 0.0) return false;
   return o.kernel == 2 || (o.kernel == 0 && !wave_chosen(r.m1, r.m2, r.n1, r.n2, r.s));
 }
@@ -325,6 +382,14 @@ int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, i
   OmpArgs<T> a = omp_args<T>(r, b, o, pl);
   a.sums_side = sums_side;
   a.sums_part = b.part;
+  if constexpr (sizeof(T) == 4) {
+    if (o.prec == SDL_MIXED_BF16) {
+      if (sums_side != 0) return fail(SDL_E_UNSUPPORTED, "SDL_MIXED_BF16 has no fused sums");
+      SDL_TRY(L.begin(0));
+      HIP_TRY(launch_omp_mixed(a, L.st));
+      return L.end();
+    }
+  }
   const bool fast = use_fast<T>(r, o);
   if (o.kernel == 2 && !fast)
     return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for m=%dx%d n=%dx%d s=%d in this precision", r.m1,
@@ -469,9 +534,10 @@ int sparse_code_impl(const sdl_problem* p, int nprob, const Opt& o, hipStream_t 
   SDL_TRY(get_ctx(st, &ctx));
   Plan pl;
   layout(p, nprob, sizeof(T), 0, nullptr, &pl);
-  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
-  layout(p, nprob, sizeof(T), 0, ctx->ws, &pl);
-  pl.ybf16 = o.prec == SDL_BF16;
+  void* wsb = nullptr;
+  SDL_TRY(acquire_ws(ctx, o, pl.bytes, st, &wsb));
+  layout(p, nprob, sizeof(T), 0, wsb, &pl);
+  pl.ybf16 = o.prec == SDL_BF16 || o.prec == SDL_MIXED_BF16;
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, o.timing != 0 && o.stats != nullptr, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));
@@ -493,9 +559,10 @@ int tmod_update_impl(sdl_problem* p, int nprob, uint32_t sides, const Opt& o, hi
   SDL_TRY(get_ctx(st, &ctx));
   Plan pl;
   layout(p, nprob, sizeof(T), 0, nullptr, &pl);
-  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
-  layout(p, nprob, sizeof(T), 0, ctx->ws, &pl);
-  pl.ybf16 = o.prec == SDL_BF16;
+  void* wsb = nullptr;
+  SDL_TRY(acquire_ws(ctx, o, pl.bytes, st, &wsb));
+  layout(p, nprob, sizeof(T), 0, wsb, &pl);
+  pl.ybf16 = o.prec == SDL_BF16 || o.prec == SDL_MIXED_BF16;
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, o.timing != 0 && o.stats != nullptr, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));
@@ -509,6 +576,63 @@ int tmod_update_impl(sdl_problem* p, int nprob, uint32_t sides, const Opt& o, hi
     if (sides & 2u) SDL_TRY(run_update<T>(2, p[q], pl.pb[q], pl, true, L));
   }
   return finish_call(st, ctx, pl, o, marks, true);
+}
+
+// One node's work in Algorithm 1 step 1 (side 1) or step 3 (side 2): the sparse coding and the
+// reduced sums [A | B | sum res2] of its new codes, written to `sums`.
+template <typename T>
+int sparse_code_sums_impl(const sdl_problem* p, int side, double* sums, const Opt& o, hipStream_t st) {
+  Ctx* ctx;
+  SDL_TRY(get_ctx(st, &ctx));
+  Plan pl;
+  layout(p, 1, sizeof(T), 0, nullptr, &pl);
+  void* wsb = nullptr;
+  SDL_TRY(acquire_ws(ctx, o, pl.bytes, st, &wsb));
+  layout(p, 1, sizeof(T), 0, wsb, &pl);
+  pl.ybf16 = o.prec == SDL_BF16 || o.prec == SDL_MIXED_BF16;
+  std::vector<std::pair<int, int>> marks;
+  Launcher L{st, o.timing != 0 && o.stats != nullptr, ctx, &marks};
+  SDL_TRY(begin_call(st, ctx, pl, 1));
+  if (o.check_finite) {
+    SDL_TRY(run_check_finite<T>(p, 1, pl, st));
+    SDL_TRY(finish_call(st, ctx, pl, o, marks, true));
+  }
+  const sdl_problem& r = p[0];
+  const PBuf& b = pl.pb[0];
+  const int na = side == 1 ? r.n1 : r.n2, mr = side == 1 ? r.m1 : r.m2;
+  const int nent = na * na + mr * na;
+  if (r.N == 0) {
+    HIP_TRY(launch_fill_double(sums, nent + 1, 0.0, st));
+    return finish_call(st, ctx, pl, o, marks, false);
+  }
+  SDL_TRY(run_prep<T>(r, b, L));
+  hipError_t e;
+  const double* src = nullptr;
+  if (o.prec != SDL_MIXED_BF16 && use_fast<T>(r, o)) {
+    // sums accumulated in the sparse-coding launch (one row of nent + 1 per workgroup)
+    const int rows = omp_fast_partial_rows(r.N, r.m1, r.m2, r.n1, r.n2, r.s);
+    SDL_TRY(run_omp<T>(r, b, o, pl, side, L));
+    SDL_TRY(L.begin(2));
+    const int nrow = launch_reduce_stage1(b.part, rows, nent + 1, b.stage, &src, st, &e);
+    HIP_TRY(e);
+    HIP_TRY(launch_reduce_final(src, nrow, nent + 1, nent + 1, sums, st));
+    SDL_TRY(L.end());
+  } else {
+    SDL_TRY(run_omp<T>(r, b, o, pl, 0, L));
+    const TmodArgs<T> a = tmod_args<T>(side, r, b, pl);
+    const int nblk = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2, r.s, r.n2, sizeof(T))
+                                : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1, r.s, r.n1, sizeof(T));
+    SDL_TRY(L.begin(1));
+    HIP_TRY(launch_tmod_sums<T>(a, b.part, st));
+    SDL_TRY(L.end());
+    SDL_TRY(L.begin(2));
+    const int nrow = launch_reduce_stage1(b.part, nblk, nent, b.stage, &src, st, &e);
+    HIP_TRY(e);
+    HIP_TRY(launch_reduce_final(src, nrow, nent, nent, sums, st));
+    HIP_TRY(launch_sum_res2<T>((const T*)r.res2, r.N, b.rpart, b.rblk, sums + nent, st));
+    SDL_TRY(L.end());
+  }
+  return finish_call(st, ctx, pl, o, marks, false);
 }
 
 int validate_learned(const sdl_problem* p, int nprob, const Opt& o) {
@@ -616,6 +740,28 @@ int one_iteration_branched(sdl_problem* p, int nprob, int K, const Opt& o, const
   return SDL_OK;
 }
 
+// Everything a captured learning graph bakes in: the problems (pointers and shapes), the
+// iterations per graph and K (the RMSE trace offsets), the options that select kernels or
+// enter kernel arguments, the workspace base and the kernel choices in force.  A later call
+// with an equal key replays the instantiated graph instead of capturing it again.
+std::vector<unsigned char> graph_key(const sdl_problem* p, int nprob, int K, int per, const Opt& o, const void* ws) {
+  std::vector<unsigned char> k;
+  auto put = [&k](const void* v, size_t n) {
+    const unsigned char* b = (const unsigned char*)v;
+    k.insert(k.end(), b, b + n);
+  };
+  put(p, sizeof(sdl_problem) * (size_t)nprob);
+  const long epoch = tuning_epoch();
+  const int ints[] = {nprob, K, per, o.prec, o.schedule, o.kernel};
+  const double dbl[] = {o.stop_rel, o.dep_eps, o.pivot_fp64, o.tau, o.err2, o.tie_band};
+  put(ints, sizeof(ints));
+  put(dbl, sizeof(dbl));
+  put(&o.proposer, sizeof(o.proposer));
+  put(&ws, sizeof(ws));
+  put(&epoch, sizeof(epoch));
+  return k;
+}
+
 template <typename T>
 int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hipStream_t st) {
   Ctx* ctx;
@@ -625,9 +771,10 @@ int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hi
     if (p[q].N > 0 && !p[q].res2) return fail(SDL_E_INVAL, "problem %d: sdl_learn needs res2", q);
   Plan pl;
   layout(p, nprob, sizeof(T), K, nullptr, &pl);
-  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
-  layout(p, nprob, sizeof(T), K, ctx->ws, &pl);
-  pl.ybf16 = o.prec == SDL_BF16;
+  void* wsb = nullptr;
+  SDL_TRY(acquire_ws(ctx, o, pl.bytes, st, &wsb));
+  layout(p, nprob, sizeof(T), K, wsb, &pl);
+  pl.ybf16 = o.prec == SDL_BF16 || o.prec == SDL_MIXED_BF16;
   std::vector<std::pair<int, int>> marks;
   const bool timing = o.timing != 0 && o.stats != nullptr;
   Launcher L{st, timing, ctx, &marks};
@@ -647,26 +794,38 @@ int learn_impl(sdl_problem* p, int nprob, int K, double* trace, const Opt& o, hi
     HIP_TRY(hipEventRecord(ctx->join_a, st));
     HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->join_a, 0));
     Launcher G{ctx->side, false, ctx, &marks};
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
     const int per = K < kItersPerGraph ? K : kItersPerGraph;
-    HIP_TRY(hipStreamBeginCapture(ctx->side, hipStreamCaptureModeRelaxed));
-    int rc = SDL_OK;
-    for (int it = 0; it < per && rc == SDL_OK; ++it) rc = one_iteration_branched<T>(p, nprob, K, o, pl, G, ctx);
-    hipError_t ce = hipStreamEndCapture(ctx->side, &g);
-    if (rc != SDL_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
+    std::vector<unsigned char> key = graph_key(p, nprob, K, per, o, wsb);
+    if (!ctx->gexec || key != ctx->gkey) {
+      if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+      if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+      ctx->gexec = nullptr;
+      ctx->graph = nullptr;
+      ctx->gkey.clear();
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(ctx->side, hipStreamCaptureModeRelaxed));
+      int rc = SDL_OK;
+      for (int it = 0; it < per && rc == SDL_OK; ++it) rc = one_iteration_branched<T>(p, nprob, K, o, pl, G, ctx);
+      hipError_t ce = hipStreamEndCapture(ctx->side, &g);
+      if (rc != SDL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      HIP_TRY(ce);
+      hipGraphExec_t ge = nullptr;
+      hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        HIP_TRY(ie);
+      }
+      ctx->graph = g;
+      ctx->gexec = ge;
+      ctx->gkey.swap(key);
     }
-    HIP_TRY(ce);
-    HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-    for (int it = 0; it + per <= K; it += per) HIP_TRY(hipGraphLaunch(ge, ctx->side));
+    for (int it = 0; it + per <= K; it += per) HIP_TRY(hipGraphLaunch(ctx->gexec, ctx->side));
     for (int it = 0; it < K % per; ++it) SDL_TRY(one_iteration<T>(p, nprob, K, o, pl, G));
     HIP_TRY(hipEventRecord(ctx->join_b, ctx->side));
     HIP_TRY(hipStreamWaitEvent(st, ctx->join_b, 0));
-    HIP_TRY(hipStreamSynchronize(st));
-    HIP_TRY(hipGraphExecDestroy(ge));
-    HIP_TRY(hipGraphDestroy(g));
   } else {
     for (int it = 0; it < K; ++it) SDL_TRY(one_iteration<T>(p, nprob, K, o, pl, L));
   }
@@ -736,12 +895,53 @@ void sdl_default_options(sdl_options* o) {
   o->proposer = nullptr;
   o->tau = 0.0;
   o->err2 = 0.0;
+  o->tie_band = 1.0 / 64.0;
+  o->fallback_margin = 1.01;
+  o->deterministic = 1;
+  o->reserved0 = 0;
+  o->workspace = nullptr;
+  o->workspace_bytes = 0;
+}
+
+int sdl_sparse_code_sums(const sdl_problem* p, int32_t side, double* sums, const sdl_options* o, void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  SDL_TRY(validate(p, 1, opt, false));
+  if (side != 1 && side != 2) return fail(SDL_E_INVAL, "side = %d (1 or 2)", side);
+  if (!sums) return fail(SDL_E_INVAL, "sums is NULL");
+  if (p->N > 0 && !p->res2) return fail(SDL_E_INVAL, "sdl_sparse_code_sums needs res2");
+  if (opt.err2 > 0.0 && (opt.kernel == 2 || opt.kernel == 3))
+    return fail(SDL_E_UNSUPPORTED, "the error-driven stop runs on the generic kernel (kernel 0 or 1)");
+  SDL_TRY(check_workspace(p, 1, 0, opt));
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? sparse_code_sums_impl<double>(p, side, sums, opt, st)
+                              : sparse_code_sums_impl<float>(p, side, sums, opt, st);
+}
+
+int sdl_mixed_supported(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s) {
+  return omp_mixed_supported(m1, m2, n1, n2, s) ? 1 : 0;
+}
+
+int sdl_workspace_bytes(const sdl_problem* p, int32_t nprob, int32_t call, int32_t K, const sdl_options* o,
+                        size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(SDL_E_INVAL, "bytes is NULL");
+  Opt opt = resolve(o);
+  SDL_TRY(validate(p, nprob, opt, false));
+  if (call < 0 || call > 3) return fail(SDL_E_INVAL, "call = %d (0..3)", call);
+  if (K < 0) return fail(SDL_E_INVAL, "K = %d < 0", K);
+  if (call == 3 && nprob != 1) return fail(SDL_E_INVAL, "sdl_sparse_code_sums takes one problem");
+  Plan pl;
+  layout(p, nprob, opt.prec == SDL_FP64 ? 8 : 4, call == 2 ? K : 0, nullptr, &pl);
+  *bytes = pl.bytes;
+  return SDL_OK;
 }
 
 int sdl_sparse_code(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream) {
   g_err.clear();
   Opt opt = resolve(o);
   SDL_TRY(validate(p, nprob, opt, false));
+  SDL_TRY(check_workspace(p, nprob, 0, opt));
   hipStream_t st = (hipStream_t)stream;
   return opt.prec == SDL_FP64 ? sparse_code_impl<double>(p, nprob, opt, st) : sparse_code_impl<float>(p, nprob, opt, st);
 }
@@ -751,6 +951,7 @@ int sdl_tmod_update(sdl_problem* p, int32_t nprob, uint32_t sides, const sdl_opt
   Opt opt = resolve(o);
   SDL_TRY(validate(p, nprob, opt, true));
   if (sides < 1 || sides > 3) return fail(SDL_E_INVAL, "sides = %u (1, 2 or 3)", sides);
+  SDL_TRY(check_workspace(p, nprob, 0, opt));
   hipStream_t st = (hipStream_t)stream;
   return opt.prec == SDL_FP64 ? tmod_update_impl<double>(p, nprob, sides, opt, st)
                               : tmod_update_impl<float>(p, nprob, sides, opt, st);
@@ -762,6 +963,7 @@ int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, cons
   SDL_TRY(validate(p, nprob, opt, false));
   SDL_TRY(validate_learned(p, nprob, opt));
   if (K < 0) return fail(SDL_E_INVAL, "K = %d < 0", K);
+  SDL_TRY(check_workspace(p, nprob, K, opt));
   hipStream_t st = (hipStream_t)stream;
   return opt.prec == SDL_FP64 ? learn_impl<double>(p, nprob, K, rmse_trace, opt, st)
                               : learn_impl<float>(p, nprob, K, rmse_trace, opt, st);
@@ -772,15 +974,17 @@ int sdl_autotune(const sdl_problem* p, int32_t nprob, int32_t reps, const sdl_op
   Opt opt = resolve(o);
   SDL_TRY(validate(p, nprob, opt, false));
   if (reps < 1) return fail(SDL_E_INVAL, "reps = %d < 1", reps);
-  if (opt.prec == SDL_FP64) return SDL_OK;  // the register-resident kernels are FP32
+  SDL_TRY(check_workspace(p, nprob, 0, opt));
+  if (opt.prec == SDL_FP64 || opt.prec == SDL_MIXED_BF16) return SDL_OK;  // FP32 register-resident kernels only
   hipStream_t st = (hipStream_t)stream;
   Ctx* ctx;
   SDL_TRY(get_ctx(st, &ctx));
   Plan pl;
   layout(p, nprob, sizeof(float), 0, nullptr, &pl);
-  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
-  layout(p, nprob, sizeof(float), 0, ctx->ws, &pl);
-  pl.ybf16 = opt.prec == SDL_BF16;
+  void* wsb = nullptr;
+  SDL_TRY(acquire_ws(ctx, opt, pl.bytes, st, &wsb));
+  layout(p, nprob, sizeof(float), 0, wsb, &pl);
+  pl.ybf16 = opt.prec == SDL_BF16 || opt.prec == SDL_MIXED_BF16;
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, false, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));
@@ -821,7 +1025,7 @@ int sdl_probe_hbm_copy(void* dst, const void* src, size_t bytes, int32_t reps, d
 int sdl_probe_peak(int32_t kind, void* sink, int32_t reps, double* tflops, void* stream) {
   g_err.clear();
   if (!sink || !tflops) return fail(SDL_E_INVAL, "NULL argument");
-  if (kind < 0 || kind > 3) return fail(SDL_E_INVAL, "kind = %d (0..3)", kind);
+  if (kind < 0 || kind > 6) return fail(SDL_E_INVAL, "kind = %d (0..6)", kind);
   if (reps < 1) return fail(SDL_E_INVAL, "reps = %d < 1", reps);
   HIP_TRY(probe_peak(kind, (float*)sink, reps, (hipStream_t)stream, tflops));
   return SDL_OK;
@@ -893,6 +1097,7 @@ int sdl_learned_sparse_code(sdl_proposer* P, const sdl_problem* p, int32_t nprob
   opt.prec = SDL_FP32;
   opt.proposer = P;
   SDL_TRY(validate(p, nprob, opt, false));
+  SDL_TRY(check_workspace(p, nprob, 0, opt));
   SDL_TRY(validate_learned(p, nprob, opt));
   if (accept && nprob != 1) return fail(SDL_E_INVAL, "accept needs nprob == 1");
   hipStream_t st = (hipStream_t)stream;
@@ -900,9 +1105,10 @@ int sdl_learned_sparse_code(sdl_proposer* P, const sdl_problem* p, int32_t nprob
   SDL_TRY(get_ctx(st, &ctx));
   Plan pl;
   layout(p, nprob, sizeof(float), 0, nullptr, &pl);
-  SDL_TRY(ensure_ws(ctx, pl.bytes, st));
-  layout(p, nprob, sizeof(float), 0, ctx->ws, &pl);
-  pl.ybf16 = opt.prec == SDL_BF16;
+  void* wsb = nullptr;
+  SDL_TRY(acquire_ws(ctx, opt, pl.bytes, st, &wsb));
+  layout(p, nprob, sizeof(float), 0, wsb, &pl);
+  pl.ybf16 = opt.prec == SDL_BF16 || opt.prec == SDL_MIXED_BF16;
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, false, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));
@@ -923,11 +1129,14 @@ int sdl_learned_sparse_code(sdl_proposer* P, const sdl_problem* p, int32_t nprob
   return finish_call(st, ctx, pl, opt, marks, opt.stats != nullptr);
 }
 
-int sdl_proposer_calibrate(sdl_proposer* P, const sdl_problem* prob, double violation, double* tau_out,
-                           void* stream) {
+int sdl_proposer_calibrate(sdl_proposer* P, const sdl_problem* prob, double violation, const sdl_options* opts,
+                           double* tau_out, void* stream) {
   g_err.clear();
   if (!P || !prob || !tau_out) return fail(SDL_E_INVAL, "NULL argument");
   if (!(violation >= 0.0 && violation < 1.0)) return fail(SDL_E_INVAL, "violation must be in [0, 1)");
+  const Opt copt = resolve(opts);
+  if (!(copt.fallback_margin >= 1.0)) return fail(SDL_E_INVAL, "fallback_margin must be >= 1");
+  const double margin = copt.fallback_margin;
   const sdl_problem& r = *prob;
   if (!r.res2) return fail(SDL_E_INVAL, "calibration needs res2");
   const int64_t N = r.N;
@@ -950,7 +1159,7 @@ int sdl_proposer_calibrate(sdl_proposer* P, const sdl_problem* prob, double viol
     double yy = 0.0;
     for (int e = 0; e < r.m1 * r.m2; ++e) yy += (double)y[k * r.m1 * r.m2 + e] * y[k * r.m1 * r.m2 + e];
     const double ratio = yy > 0 ? rp[k] / yy : 0.0;
-    const int bad = (double)rp[k] > 1.01 * (double)ro[k] ? 1 : 0;
+    const int bad = (double)rp[k] > margin * (double)ro[k] ? 1 : 0;
     q[k] = {ratio, bad};
   }
   std::sort(q.begin(), q.end());

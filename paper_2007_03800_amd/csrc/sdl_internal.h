@@ -33,6 +33,7 @@ struct OmpArgs {
   T* res2;  // may be null
   double stop_rel, dep_eps, pivot_fp64;
   double err2;  // > 0: error-driven stop (generic kernel only), residual energy target
+  double tie_band;  // SDL_MIXED_BF16: relative band of BF16 near-ties re-scored in FP32
   unsigned long long* counters;  // kNumCounters entries
   // Register-resident kernel only: also accumulate the TMOD sums of the new codes for
   // side sums_side (1: D1 update, 2: D2 update; 0: none) plus the sum of res2, one
@@ -48,7 +49,7 @@ struct OmpArgs {
 // Buffers describing one TMOD half-step for one problem.
 template <typename T>
 struct TmodArgs {
-  int side;  // 1: update D1 (Corollary 1), 2: update D2 (Proposition 1)
+  int side;  // 1: update D1 (Corollary 1), 2: update D2 (Result 1)
   int m1, m2, n1, n2, s;
   int64_t N;
   const T* Y;
@@ -94,6 +95,10 @@ hipError_t launch_omp_wave(const OmpArgs<T>& a, hipStream_t st);
 // form of the standalone-sums path for the shapes it is compiled for (launch_omp_wave
 // dispatches to it); no index mode, no sums epilogue.
 bool omp_quad_supported(int m1, int m2, int n1, int n2, int s);
+// SDL_MIXED_BF16 sparse coding (omp_mixed.hip): correlations D1^T R D2 on the BF16 matrix
+// cores every step, near-ties re-scored in FP32; shapes it is compiled for.
+bool omp_mixed_supported(int m1, int m2, int n1, int n2, int s);
+hipError_t launch_omp_mixed(const OmpArgs<float>& a, hipStream_t st);
 hipError_t launch_omp_quad(const OmpArgs<float>& a, hipStream_t st);
 // Matrix-core variants (omp_mfma.hip): four lanes per signal, refresh on 4x4x1 MFMA.
 struct MfmaVariant {
@@ -121,6 +126,8 @@ hipError_t omp_fast_init_device();
 void omp_fast_set_choice(int m1, int m2, int n1, int n2, int s, int id);
 hipError_t autotune_problem(const OmpArgs<float>& a, hipStream_t st, int reps, int* chosen, double* best_ms);
 bool tuned_config(int m1, int m2, int n1, int n2, int s, int* lr, int* lc, int* wpe, int* mfma, double* ms);
+// Counter bumped whenever a kernel choice (autotuned or forced) changes.
+long tuning_epoch();
 size_t omp_generic_lds_bytes(int m1, int m2, int n1, int n2, int s, size_t elem);
 hipError_t omp_generic_init_device();
 
@@ -140,6 +147,12 @@ hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, hipStream_t st);
 int launch_reduce_stage1(const double* part, int P, int ld, double* stage, const double** src, hipStream_t st,
                          hipError_t* err);
 int reduce_stage_rows(int P);
+// The last stage alone: out[e] = row-order sum of the nrow rows at src (stride ld), e < n.
+hipError_t launch_reduce_final(const double* src, int nrow, int ld, int n, double* out, hipStream_t st);
+// *out = sum of res2[0 .. N-1] in a fixed order (nblk = rmse_num_blocks(N) partials in part).
+template <typename T>
+hipError_t launch_sum_res2(const T* res2, int64_t N, double* part, int nblk, double* out, hipStream_t st);
+hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st);
 // Optional RMSE output of the solve kernel: trace[*counter + offset] = sqrt(sums[idx] / denom), then ++*counter.
 struct RmseOut {
   double* trace;  // null: no RMSE

@@ -1,8 +1,8 @@
-// TMOD dictionary update kernels (Algorithm 1 steps 1-4; Corollary 1, Proposition 1).
+// TMOD dictionary update kernels (Algorithm 1 steps 1-4; Corollary 1, Result 1).
 //
 // Side 1 (D1 update, Corollary 1):  T_k = X_k D2^T (n1 x m2)
 //     A = sum_k T_k T_k^T (n1 x n1),  B = sum_k Y_k T_k^T (m1 x n1),  D1* = B A^{-1}
-// Side 2 (D2 update, Proposition 1): Z_k = D1 X_k (m1 x n2), U_k = Z_k^T
+// Side 2 (D2 update, Result 1): Z_k = D1 X_k (m1 x n2), U_k = Z_k^T
 //     A = sum_k Z_k^T Z_k (n2 x n2),  B = sum_k Y_k^T Z_k (m2 x n2),  D2* = B A^{-1}
 // Both are written once with "row atoms" ra (i for side 1, j for side 2), the
 // signal seen as Yt (Y for side 1, Y^T for side 2) and the fixed dictionary Do
@@ -35,6 +35,16 @@ __global__ void reduce_stage1_kernel(const double* __restrict__ part, int P, int
 #pragma unroll 16
   for (int b = c * kChunk; b < b1; ++b) v += part[(size_t)b * nent + e];
   stage[(size_t)c * nent + e] = v;
+}
+
+// The last reduction stage alone: out[e] = sum over the nrow rows of src (row stride ld)
+// in row order, for e < n (the same order as the solve kernel's first stage).
+__global__ void reduce_final_kernel(const double* __restrict__ src, int nrow, int ld, int n, double* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double v = 0.0;
+  for (int b = 0; b < nrow; ++b) v += src[(size_t)b * ld + e];
+  out[e] = v;
 }
 
 constexpr int kSolveThreads = 512;
@@ -115,6 +125,18 @@ __global__ void __launch_bounds__(kRmseThreads) rmse_partial_kernel(const T* res
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+__global__ void sum_final_kernel(const double* part, int nblk, double* out) {
+  if (threadIdx.x != 0) return;
+  double v = 0.0;
+  for (int b = 0; b < nblk; ++b) v += part[b];
+  *out = v;
+}
+
+__global__ void fill_double_kernel(double* p, int n, double v) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
 __global__ void rmse_final_kernel(const double* part, int nblk, double denom, double* trace, int stride, int offset,
                                   int* counter) {
   if (threadIdx.x != 0) return;
@@ -167,6 +189,17 @@ int launch_reduce_stage1(const double* part, int P, int ld, double* stage, const
 
 int reduce_stage_rows(int P) { return (P + kChunk - 1) / kChunk; }
 
+hipError_t launch_reduce_final(const double* src, int nrow, int ld, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_final_kernel, dim3((n + 255) / 256), dim3(256), 0, st, src, nrow, ld, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_double_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_tmod_solve(const double* src, int nrow, int ld, double* sums, int mr, int na, double* D, T* Dc,
                              double* G64, T* Gc, double* w, int* status, unsigned long long* counters,
@@ -217,6 +250,13 @@ hipError_t launch_rmse(const T* res2, int64_t N, double denom, double* part, int
 }
 
 template <typename T>
+hipError_t launch_sum_res2(const T* res2, int64_t N, double* part, int nblk, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(rmse_partial_kernel<T>, dim3(nblk), dim3(kRmseThreads), 0, st, res2, N, nblk, part);
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(64), 0, st, part, nblk, out);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_check_finite(const T* x, int64_t n, int* status, hipStream_t st) {
   if (n == 0) return hipSuccess;
   int64_t g = (n + 255) / 256;
@@ -246,7 +286,8 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st) {
                                         hipStream_t);                                                         \
   template hipError_t launch_rmse<T>(const T*, int64_t, double, double*, int, double*, int, int, int*,        \
                                      hipStream_t);                                                            \
-  template hipError_t launch_check_finite<T>(const T*, int64_t, int*, hipStream_t);
+  template hipError_t launch_check_finite<T>(const T*, int64_t, int*, hipStream_t);                          \
+  template hipError_t launch_sum_res2<T>(const T*, int64_t, double*, int, double*, hipStream_t);
 SDL_INST(float)
 SDL_INST(double)
 #undef SDL_INST

@@ -1,5 +1,5 @@
 // Device routine of the TMOD dictionary update: the FP64 solve on the used atoms with
-// normalisation (Corollary 1 / Proposition 1), which also rewrites the compute-type
+// normalisation (Corollary 1 / Result 1), which also rewrites the compute-type
 // dictionary copy and the Gram matrix.
 #pragma once
 

@@ -1,7 +1,7 @@
 // TMOD partial sums on the matrix cores (Algorithm 1 steps 1 and 3).
 //
 // Side 1 (Corollary 1):  T_k = X_k D2^T (n1 x m2),  A = sum T_k T_k^T,  B = sum Y_k T_k^T
-// Side 2 (Proposition 1): U_k = (D1 X_k)^T (n2 x m1), A = sum U_k U_k^T, B = sum Y_k^T U_k^T
+// Side 2 (Result 1): U_k = (D1 X_k)^T (n2 x m1), A = sum U_k U_k^T, B = sum Y_k^T U_k^T
 //
 // For a batch of bs signals the per-signal factors are laid side by side,
 // Tcat = [T_1 ... T_bs] (na x K) and Ycat = [Yt_1 ... Yt_bs] (mr x K) with

@@ -6,9 +6,14 @@ def kron_cols(d1, d2):
     return np.kron(d2, d1)
 
 
-def near_tie_ok(Y, d1, d2, prefix, gpu_atom, oracle_atom, band):
-    """At the first diverging step, is the GPU's pick within ``band`` (relative) of the best
-    unselected |correlation|?  Residual of the common prefix is taken by numpy lstsq on the
+# Coefficient error floor: a coefficient's error is measured relative to max(|x|, COEF_FLOOR * the
+# largest |x| of its signal), so a coefficient far below its signal's scale is held to that scale.
+COEF_FLOOR = 2e-2
+
+
+def tie_gap(Y, d1, d2, prefix, gpu_atom, oracle_atom):
+    """At the first diverging step: (|corr| of the best unselected atom - |corr| of the GPU's pick,
+    the best |corr|, ||Y||_F).  The residual of the common prefix is taken by numpy lstsq on the
     explicit Kronecker columns, independently of both implementations."""
     K = kron_cols(d1, d2)
     y = Y.flatten("F")
@@ -20,28 +25,55 @@ def near_tie_ok(Y, d1, d2, prefix, gpu_atom, oracle_atom, band):
     c = np.abs(K.T @ r)
     c[prefix] = -1
     top = c.max()
-    return c[gpu_atom] >= top * (1 - band) and c[oracle_atom] >= top * (1 - band)
+    return top - min(c[gpu_atom], c[oracle_atom]), top, float(np.linalg.norm(y))
 
 
-def compare_codes(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band, coef_rtol):
-    """Returns (n_agree, n_near_tie, n_bad, max coef rel err on agreeing signals)."""
+def code_stats(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band):
+    """Supports and coefficients of the GPU against the oracle's.
+
+    A signal whose support differs is a classified near-tie when, at the first step where the two
+    selections diverge, both picks' exact correlations are within band * (the best one) of the best
+    (band: 1e-9 for FP64 arithmetic, 1e-4 for FP32); otherwise it counts as bad.  Coefficients are
+    compared on the signals whose supports agree, element by element:
+    |x_gpu - x_ref| / max(|x_ref|, COEF_FLOOR * max_t |x_ref|)."""
     agree = np.all(supp_g == supp_o, axis=1)
-    bad = 0
-    ties = 0
+    bad, ties, gaps = 0, 0, []
     for k in np.nonzero(~agree)[0]:
         t = int(np.argmax(supp_g[k] != supp_o[k]))
         prefix = [int(a) for a in supp_o[k, :t]]
         ga, oa = int(supp_g[k, t]), int(supp_o[k, t])
-        if ga >= 0 and oa >= 0 and near_tie_ok(Y[k], d1, d2, prefix, ga, oa, band):
-            ties += 1
+        if ga >= 0 and oa >= 0:
+            gap, top, yn = tie_gap(Y[k], d1, d2, prefix, ga, oa)
+            gaps.append((int(k), t, gap / top, gap / yn))
+            if gap <= band * top:
+                ties += 1
+                continue
         else:
-            bad += 1
-    err = 0.0
+            gaps.append((int(k), t, float("nan"), float("nan")))
+        bad += 1
+    err, worst, norm_err = 0.0, None, 0.0
     if agree.any():
-        num = np.abs(coef_g[agree] - coef_o[agree]).max(axis=1)
-        den = np.abs(coef_o[agree]).max(axis=1) + 1e-300
-        err = float((num / den).max())
-    return int(agree.sum()), ties, bad, err
+        ref = coef_o[agree]
+        mx = np.abs(ref).max(axis=1, keepdims=True)
+        scale = np.maximum(np.abs(ref), COEF_FLOOR * mx) + 1e-300
+        e = np.abs(coef_g[agree] - ref) / scale
+        err = float(e.max())
+        i, t = np.unravel_index(int(np.argmax(e)), e.shape)
+        worst = (float(np.abs(ref[i, t]) / (mx[i, 0] + 1e-300)), float(np.abs(coef_g[agree][i, t] - ref[i, t])
+                                                                          / (mx[i, 0] + 1e-300)))
+        norm_err = float((np.linalg.norm(coef_g[agree] - ref, axis=1) / (np.linalg.norm(ref, axis=1) + 1e-300)).max())
+    return dict(agree=int(agree.sum()), ties=ties, bad=bad, coef_err=err, gaps=gaps, worst=worst,
+                norm_err=norm_err)
+
+
+def compare_codes(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band, coef_rtol=None):
+    """Returns (n_agree, n_near_tie, n_bad, max element-wise coefficient error) as code_stats defines them."""
+    st = code_stats(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band)
+    if st["bad"]:
+        print("unclassified support mismatches (signal, step, gap/best, gap/||Y||):", st["gaps"][:10])
+    print("coefficients: element-wise err %.2e (worst at |x|/max %.2e, |dx|/max %.2e), normwise err %.2e"
+          % (st["coef_err"], *(st["worst"] or (0.0, 0.0)), st["norm_err"]))
+    return st["agree"], st["ties"], st["bad"], st["coef_err"]
 
 
 def full_size_checks(Ym, pr, s, fresh, n_each=1000, seed=11):

@@ -20,7 +20,7 @@ def test_header_symbols_exported():
     lib = _native.lib()
     for n in names:
         assert hasattr(lib, n)
-    assert lib.sdl_abi_version() == 4
+    assert lib.sdl_abi_version() == 5
 
 
 def _problem(**kw):
@@ -83,6 +83,74 @@ def test_default_options():
     assert o.prec == 0 and o.use_graph == 1 and o.schedule == 0
     assert o.stop_rel < 0 and o.dep_eps < 0 and o.pivot_fp64 < 0
     assert o.err2 == 0.0
+    assert o.tie_band == 2.0 ** -6 and o.fallback_margin == 1.01 and o.deterministic == 1
+    assert o.reserved0 == 0 and not o.workspace and o.workspace_bytes == 0
+
+
+@pytest.mark.parametrize("field,value", [("tie_band", -0.1), ("tie_band", 0.5), ("tie_band", float("nan")),
+                                         ("fallback_margin", 0.99), ("fallback_margin", float("nan")),
+                                         ("deterministic", 2), ("reserved0", 1)])
+@pytest.mark.parametrize("fn", ["sparse_code", "tmod_update", "learn"])
+def test_option_validation(fn, field, value):
+    o = _native.default_options()
+    setattr(o, field, value)
+    assert _call(fn, _problem(), o) == -1
+
+
+def test_workspace_validation():
+    """A caller workspace that is misaligned or too small is refused before any device work;
+    its required size comes from a host-only query."""
+    lib = _native.lib()
+    arr = (_native.Problem * 1)(_problem(N=100000))
+    o = _native.default_options()
+    o.prec = _native.SDL_FP32
+    need = ctypes.c_size_t()
+    for call, K in ((0, 0), (1, 0), (2, 20), (3, 0)):
+        assert lib.sdl_workspace_bytes(arr, 1, call, K, ctypes.byref(o), ctypes.byref(need)) == 0
+        assert need.value > 0
+    assert lib.sdl_workspace_bytes(arr, 1, 4, 0, ctypes.byref(o), ctypes.byref(need)) == -1
+    lib.sdl_workspace_bytes(arr, 1, 0, 0, ctypes.byref(o), ctypes.byref(need))
+    o.workspace, o.workspace_bytes = 256, need.value - 1
+    assert lib.sdl_sparse_code(arr, 1, ctypes.byref(o), None) == -4
+    o.workspace, o.workspace_bytes = 257, need.value
+    assert lib.sdl_sparse_code(arr, 1, ctypes.byref(o), None) == -1
+    o.workspace, o.workspace_bytes = 256, 0
+    assert lib.sdl_sparse_code(arr, 1, ctypes.byref(o), None) == -1
+
+
+def test_sparse_code_sums_validation():
+    lib = _native.lib()
+    o = _native.default_options()
+    arr = (_native.Problem * 1)(_problem())
+    assert lib.sdl_sparse_code_sums(arr, 0, 8, ctypes.byref(o), None) == -1
+    assert lib.sdl_sparse_code_sums(arr, 3, 8, ctypes.byref(o), None) == -1
+    assert lib.sdl_sparse_code_sums(arr, 1, None, ctypes.byref(o), None) == -1
+    arr = (_native.Problem * 1)(_problem(res2=None))
+    assert lib.sdl_sparse_code_sums(arr, 1, 8, ctypes.byref(o), None) == -1
+    arr = (_native.Problem * 1)(_problem(s=257))
+    assert lib.sdl_sparse_code_sums(arr, 1, 8, ctypes.byref(o), None) == -2
+
+
+def test_mixed_precision_validation():
+    """SDL_MIXED_BF16 is refused for shapes without its kernel, and with the error-driven stop."""
+    lib = _native.lib()
+    o = _native.default_options()
+    o.prec = _native.SDL_MIXED_BF16
+    assert _call("sparse_code", _problem(m1=5, m2=7, n1=9, n2=11, s=3), o) == -7
+    if lib.sdl_mixed_supported(12, 12, 24, 24, 12):
+        o.err2 = 1.0
+        assert _call("sparse_code", _problem(m1=12, m2=12, n1=24, n2=24, s=12), o) == -7
+
+
+def test_proposer_file_errors(tmp_path):
+    lib = _native.lib()
+    h = ctypes.c_void_p()
+    assert lib.sdl_proposer_load(str(tmp_path / "missing.bin").encode(), ctypes.byref(h)) == -1
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTAPROP" + bytes(40))
+    assert lib.sdl_proposer_load(str(bad).encode(), ctypes.byref(h)) == -1
+    assert not h.value
+    assert lib.sdl_proposer_save(None, str(bad).encode()) == -1
 
 
 def test_error_driven_option_validation():
@@ -104,7 +172,7 @@ def test_probe_validation():
     assert lib.sdl_probe_hbm_copy(None, None, 1024, 1, ctypes.byref(d), None) == -1
     assert lib.sdl_probe_hbm_copy(1, 2, 8, 1, ctypes.byref(d), None) == -1
     assert lib.sdl_probe_hbm_copy(1, 2, 1024, 0, ctypes.byref(d), None) == -1
-    assert lib.sdl_probe_peak(4, 1, 1, ctypes.byref(d), None) == -1
+    assert lib.sdl_probe_peak(7, 1, 1, ctypes.byref(d), None) == -1
     assert lib.sdl_probe_peak(0, None, 1, ctypes.byref(d), None) == -1
     assert lib.sdl_probe_peak(0, 1, 0, ctypes.byref(d), None) == -1
 
@@ -118,3 +186,4 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_2007_03800_amd import api
     with pytest.raises(ImportError):
         api.tuned_config(8, 8, 16, 16, 8)
+

@@ -3,10 +3,12 @@ takes atoms until its residual energy is at or below err2 = eps^2, eps = 1.15 si
 with s = m1 m2 / 2 as the cap.  The generic kernel against the FP64 oracle with the same rule.
 
 Bars: supports and coefficients as in the other parity tests (FP64 1e-10 relative, FP32 1e-4,
-agreement >= 97%); the number of atoms of a signal may differ from the oracle's only where the
-decision is a near-tie with the threshold: the oracle's residual energy at the smaller count lies
-within 1e-9 (FP64) or 2e-3 (FP32) relative of err2 (the kernel tracks the energy by the OMP
-recurrence, the oracle from the explicit residual)."""
+agreement >= 97%, every support mismatch a classified near-tie); the number of atoms of a signal
+may differ from the oracle's only where the decision is a near-tie with the threshold: the
+oracle's residual energy at the smaller count lies within 1e-9 relative of err2 (FP64), or within
+64 u ||Y_k||^2 of it in FP32 (u = 2^-24): the kernel tracks the energy by the OMP recurrence
+||R||^2 -= corr^2 / delta^2 from ||Y_k||^2 down, whose FP32 rounding error is a small multiple of
+u ||Y_k||^2, while the oracle takes it from the explicit residual."""
 import numpy as np
 import pytest
 import torch
@@ -20,7 +22,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-@pytest.mark.parametrize("dtype,band,ctol", [(torch.float64, 1e-9, 1e-10), (torch.float32, 2e-3, 1e-4)])
+@pytest.mark.parametrize("dtype,band,ctol", [(torch.float64, 1e-9, 1e-10), (torch.float32, 1e-4, 1e-4)])
 @pytest.mark.parametrize("kernel", [0, 1])
 def test_error_driven_matches_oracle(dtype, band, ctol, kernel):
     w = synth.WORKLOADS["fp32_8x8_n16_s8"]
@@ -43,7 +45,8 @@ def test_error_driven_matches_oracle(dtype, band, ctol, kernel):
     for k in np.nonzero(~same)[0]:
         t = int(min(ng[k], no[k]))
         r_t = oracle.omp(Y[k:k + 1], d1, d2, max(t, 1))[2][0] if t > 0 else float(np.sum(Y[k] ** 2))
-        assert abs(r_t / err2 - 1) <= band, (k, int(ng[k]), int(no[k]), r_t / err2)
+        tol = 1e-9 * err2 if dtype == torch.float64 else 64 * 2.0 ** -24 * float(np.sum(Y[k] ** 2))
+        assert abs(r_t - err2) <= tol, (k, int(ng[k]), int(no[k]), r_t / err2, tol / err2)
     ks = np.nonzero(same)[0]
     agree, ties, bad, err = compare_codes(Y[ks], d1, d2, sg[ks], cg[ks], so[ks], co[ks], band, ctol)
     print("%s kernel %d: nnz %d..%d (mean %.1f), count mismatches %d, agree %d/%d, ties %d, bad %d, err %.1e"
@@ -53,7 +56,7 @@ def test_error_driven_matches_oracle(dtype, band, ctol, kernel):
         ok = ks[np.all(sg[ks] == so[ks], axis=1)]
         np.testing.assert_allclose(rg[ok], ro[ok], rtol=1e-9)
     else:
-        assert (~same).sum() <= 0.01 * N and agree >= 0.97 * len(ks) and bad <= 3 and err <= ctol
+        assert (~same).sum() <= 0.01 * N and agree >= 0.97 * len(ks) and bad == 0 and err <= ctol
 
 
 def test_error_driven_off_matches_plain():
@@ -98,5 +101,5 @@ def test_learn_with_error_driven_stop_fp64(rng):
     torch.cuda.synchronize()
     nnz = np.sum(pr.supp.cpu().numpy() >= 0, axis=1)
     assert len(set(nnz.tolist())) > 2  # the stop varies per signal
-    np.testing.assert_allclose(pr.d1(), e1, rtol=1e-9, atol=1e-9)
-    np.testing.assert_allclose(pr.d2(), e2, rtol=1e-9, atol=1e-9)
+    for g, o in ((pr.d1(), e1), (pr.d2(), e2)):
+        assert np.abs(g - o).max() <= 1e-10 * np.abs(o).max()

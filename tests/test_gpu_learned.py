@@ -180,3 +180,17 @@ def test_learn_with_proposer_runs_and_tracks_plain(rng):
     b = api.Problem.from_math(Y, d1, d2, w.s)
     tb = api.learn(b, 3)[0]
     np.testing.assert_allclose(ta, tb, rtol=1e-4)
+
+
+def test_proposer_save_load_roundtrip(rng, tmp_path):
+    """sdl_proposer_save / sdl_proposer_load: same weights, same logits, same shape."""
+    net = api.Proposer(M1, M2, N1, N2, hidden=128, seed=11)
+    net.set_params(weights(rng, 128))
+    path = tmp_path / "net.bin"
+    net.save(path)
+    back = api.Proposer.load(path)
+    assert (back.m1, back.m2, back.n1, back.n2, back.hidden) == (M1, M2, N1, N2, 128)
+    np.testing.assert_array_equal(back.params(), net.params())
+    Y, _, _, _ = data(rng, 256)
+    Yd = torch.from_numpy(np.ascontiguousarray(Y.transpose(0, 2, 1))).float().cuda()
+    assert torch.equal(back.logits(Yd), net.logits(Yd))

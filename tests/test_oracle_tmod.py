@@ -40,7 +40,7 @@ def test_gram_shortcut_matches_dense_sums(rng):
 
 @pytest.mark.parametrize("side", [1, 2])
 def test_update_equals_stacked_lstsq(rng, side):
-    """Corollary 1 / Proposition 1: the update is the LS solution of the stacked system, normalised."""
+    """Corollary 1 / Result 1: the update is the LS solution of the stacked system, normalised."""
     Y, d1, d2, supp, coef = setup(rng)
     X = oracle.densify(supp, coef, d1.shape[1], d2.shape[1])
     n1d, n2d, c, w = oracle.tmod_update(side, Y, d1, d2, supp, coef)
