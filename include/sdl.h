@@ -169,6 +169,22 @@ int sdl_tmod_update(sdl_problem* p, int32_t nprob, uint32_t sides, const sdl_opt
 int sdl_learn(sdl_problem* p, int32_t nprob, int32_t K, double* rmse_trace, const sdl_options* o,
               void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): sdl_sparse_code with the same arguments, results and
+ * kernels, whose workspace (status word, counters, compute-type dictionary copies and Gram
+ * matrices) lives in a static device array of SDL_NOALLOC_SCRATCH_BYTES inside the library
+ * instead of allocated memory.  It calls no hipMalloc/hipFree or other allocating routine; each
+ * GPU the library runs on holds its own array until the process ends, set up on the first call on
+ * that device.  Every call on a GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (other streams, other threads) race and must not be issued.  Each problem takes
+ * (m1 n1 + m2 n2) e + (n1^2 + n2^2)(8 + e) bytes of the array (e = 8 for SDL_FP64, else 4, each
+ * piece rounded up to 256 bytes; at most 192 KiB for the largest FP64 shape), plus about 1 KiB per
+ * call; problems that do not fit are refused with SDL_E_NOMEM before any work is queued.
+ * options->timing and options->workspace must be 0 / NULL (SDL_E_INVAL).  Asynchronous on
+ * `stream` unless stats are requested. */
+#define SDL_NOALLOC_SCRATCH_BYTES (1u << 20)
+int sdl_sparse_code_noalloc(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream);
+
 /* The work of one node of Algorithm 1 in its step 1 (side 1) or step 3 (side 2): 2D-OMP of the
  * problem's signals as sdl_sparse_code does it (supp, coef and res2 written), then the sums that
  * node sends to the master, formed from the new codes:

@@ -257,8 +257,9 @@ struct Plan {
   size_t bytes;
 };
 
-// Lay out the workspace; with base == nullptr only measures.
-void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Plan* pl) {
+// Lay out the workspace; with base == nullptr only measures.  codes_only: only what sparse
+// coding alone uses (no partial-sum, reduction or RMSE buffers).
+void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Plan* pl, bool codes_only = false) {
   Bump b(base);
   pl->pb.resize(nprob);
   pl->status = b.take<int>(4);
@@ -274,6 +275,11 @@ void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Pla
     x.G2_64 = b.take<double>((size_t)r.n2 * r.n2);
     x.G1c = b.take<char>(elem * r.n1 * r.n1);
     x.G2c = b.take<char>(elem * r.n2 * r.n2);
+    if (codes_only) {
+      x.part = x.stage = x.sums = x.w = x.rpart = nullptr;
+      x.nblk = x.rblk = x.nent = 0;
+      continue;
+    }
     const int na = r.n1 > r.n2 ? r.n1 : r.n2, mr = r.m1 > r.m2 ? r.m1 : r.m2;
     x.nent = na * na + mr * na;
     const size_t ae = elem == 8 ? 8 : 4;  // arithmetic element size (BF16 signals compute in FP32)
@@ -551,6 +557,68 @@ int sparse_code_impl(const sdl_problem* p, int nprob, const Opt& o, hipStream_t 
     SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, 0, L));
   }
   return finish_call(st, ctx, pl, o, marks, false);
+}
+
+// ------------------------------------------------------------------ allocation-free sparse coding
+//
+// sdl_sparse_code_noalloc keeps its workspace (status word, counters, compute-type dictionary
+// copies and Gram matrices) in this file-scope device array instead of allocated memory.  Each
+// device holds its own copy; host code reaches it only through the address that
+// hipGetSymbolAddress returns for that device (kept in g_scratch_ptr), never through the
+// array's name.
+
+constexpr size_t kScratchBytes = SDL_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Once per device, with that device current: the array's device address and the kernel
+// attributes the sparse-coding kernels need (no allocation).
+int scratch_for_device(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SDL_E_DEVICE, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SDL_E_DEVICE, "hipGetSymbolAddress returned a null address for the scratch array");
+    HIP_TRY(omp_generic_init_device());
+    HIP_TRY(tmod_sums_init_device());
+    HIP_TRY(tmod_solve_init_device());
+    HIP_TRY(omp_fast_init_device());
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SDL_OK;
+}
+
+template <typename T>
+int sparse_code_noalloc_impl(const sdl_problem* p, int nprob, const Opt& o, hipStream_t st) {
+  Plan pl;
+  layout(p, nprob, sizeof(T), 0, nullptr, &pl, true);
+  if (pl.bytes > kScratchBytes)
+    return fail(SDL_E_NOMEM, "these problems need %zu bytes of workspace; the allocation-free call has %zu",
+                pl.bytes, kScratchBytes);
+  void* base = nullptr;
+  SDL_TRY(scratch_for_device(&base));
+  layout(p, nprob, sizeof(T), 0, base, &pl, true);
+  pl.ybf16 = o.prec == SDL_BF16 || o.prec == SDL_MIXED_BF16;
+  std::vector<std::pair<int, int>> marks;
+  Launcher L{st, false, nullptr, &marks};
+  SDL_TRY(begin_call(st, nullptr, pl, nprob));
+  if (o.check_finite) {
+    SDL_TRY(run_check_finite<T>(p, nprob, pl, st));
+    SDL_TRY(finish_call(st, nullptr, pl, o, marks, true));
+  }
+  for (int q = 0; q < nprob; ++q) {
+    if (p[q].N == 0) continue;
+    SDL_TRY(run_prep<T>(p[q], pl.pb[q], L));
+    SDL_TRY(run_omp<T>(p[q], pl.pb[q], o, pl, 0, L));
+  }
+  return finish_call(st, nullptr, pl, o, marks, false);
 }
 
 template <typename T>
@@ -901,6 +969,17 @@ void sdl_default_options(sdl_options* o) {
   o->reserved0 = 0;
   o->workspace = nullptr;
   o->workspace_bytes = 0;
+}
+
+int sdl_sparse_code_noalloc(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  SDL_TRY(validate(p, nprob, opt, false));
+  if (opt.timing) return fail(SDL_E_INVAL, "the allocation-free call does not time kernels (timing = 0)");
+  if (opt.workspace) return fail(SDL_E_INVAL, "the allocation-free call uses its own scratch (workspace = NULL)");
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? sparse_code_noalloc_impl<double>(p, nprob, opt, st)
+                              : sparse_code_noalloc_impl<float>(p, nprob, opt, st);
 }
 
 int sdl_sparse_code_sums(const sdl_problem* p, int32_t side, double* sums, const sdl_options* o, void* stream) {

@@ -187,3 +187,18 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     with pytest.raises(ImportError):
         api.tuned_config(8, 8, 16, 16, 8)
 
+
+def test_noalloc_refuses_before_device_work():
+    """The allocation-free call checks its fixed scratch size and its options on the host."""
+    lib = _native.lib()
+    o = _native.default_options()
+    arr = (_native.Problem * 8)(*[_problem(m1=32, m2=32, n1=64, n2=64, s=4) for _ in range(8)])
+    assert lib.sdl_sparse_code_noalloc(arr, 8, ctypes.byref(o), None) == -4
+    assert "workspace" in lib.sdl_last_error().decode()
+    o.timing = 1
+    assert lib.sdl_sparse_code_noalloc(arr, 1, ctypes.byref(o), None) == -1
+    o = _native.default_options()
+    o.workspace, o.workspace_bytes = 256, 1 << 20
+    assert lib.sdl_sparse_code_noalloc(arr, 1, ctypes.byref(o), None) == -1
+    assert lib.sdl_sparse_code_noalloc(None, 1, None, None) == -1
+
