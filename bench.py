@@ -185,7 +185,7 @@ def device_signals(synth, w, dtype, k0=0, k1=None, chunk=100_000):
     return Y
 
 
-def timed_learn(api, fresh, K, reps=3):
+def timed_learn(api, fresh, K, reps=3, **opts):
     """Autotune, one untimed run of K iterations (it also captures the learning graph), then the
     median of reps timed runs of K graph-replayed iterations of Algorithm 1, each from the initial
     dictionaries on the same buffers; returns (problems, trace, seconds)."""
@@ -200,7 +200,7 @@ def timed_learn(api, fresh, K, reps=3):
         for p, (a, b) in zip(plist, init):
             p.D1.copy_(a)
             p.D2.copy_(b)
-        traces.append(api.learn(probs, K))
+        traces.append(api.learn(probs, K, **opts))
 
     run()
     dt, _, _ = timed_runs(run, reps)
@@ -221,27 +221,44 @@ def kernel_name(api, w):
 
 def mixed_workload(api, oracle, synth):
     """Mixed precision at its own shape: 1M signals of 12x12 stored in bfloat16, 24x24 atoms,
-    s = 12, K = 10 iterations from the random initial dictionaries."""
+    s = 12, K = 10 iterations from the random initial dictionaries, with the correlations on the
+    BF16 matrix cores (SDL_MIXED_BF16); the same workload with bfloat16 storage and FP32 arithmetic
+    and with FP32 signals (the plain path) for the ratios."""
     import torch
     w = synth.WORKLOADS["mixed_12x12_n24_s12"]
     Y = device_signals(synth, w, torch.bfloat16)
     e1, e2 = synth.initial_dictionaries(w)
+    nsub = 5000
+    Ysub = Y[:nsub].double().cpu().numpy().transpose(0, 2, 1)  # the rounded signals, math layout
 
     def fresh():
         return api.Problem(Y, torch.from_numpy(e1.T.copy()).cuda(), torch.from_numpy(e2.T.copy()).cuda(), w.s)
 
-    pr, trace, dt = timed_learn(api, fresh, w.iters)
-    nsub = 5000
-    Ysub = Y[:nsub].double().cpu().numpy().transpose(0, 2, 1)  # the rounded signals, math layout
-    s_o, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
-    r_g = pr.res2[:nsub].double().cpu().numpy()
-    out = {"workload": w.name, "N": w.N, "steps": w.iters, "dtype": "bf16 signals, f32 arithmetic, f64 solves",
+    def quality(pr):
+        s_o, _, r_o = oracle.omp(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+        r_g = pr.res2[:nsub].double().cpu().numpy()
+        return {"rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
+                **support_agreement(pr.supp[:nsub].cpu().numpy(), s_o)}
+
+    pr, trace, dt = timed_learn(api, fresh, w.iters, mixed=True)
+    st = api.new_stats()
+    api.sparse_code(fresh(), mixed=True, stats=st)
+    torch.cuda.synchronize()
+    out = {"workload": w.name, "N": w.N, "steps": w.iters,
+           "dtype": "bf16 signals, bf16 matrix-core correlations with f32 accumulation, f32 near-tie re-score "
+                    "and Cholesky, f64 solves",
            "value": w.N * w.iters / dt, "unit": "signals/s per iteration", "ms_per_step": dt / w.iters * 1e3,
-           "rmse_first": float(trace[0][0]), "rmse_final": float(trace[0][-1]),
-           "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
-           **support_agreement(pr.supp[:nsub].cpu().numpy(), s_o), "omp_kernel": kernel_name(api, w)}
-    # the same workload with FP32 signals (the plain path), for the ratio
+           "rmse_first": float(trace[0][0]), "rmse_final": float(trace[0][-1]), **quality(pr),
+           "near_tie_rescored_steps_per_signal": st.near_tie_rescores / w.N,
+           "near_tie_overflow_steps_per_signal": st.near_tie_overflows / w.N,
+           "omp_kernel": "bf16 4x4x4 MFMA direct-form correlations, 16 signals per wave"}
     del pr
+    # bfloat16 storage with FP32 arithmetic
+    pb, trace_b, dtb = timed_learn(api, fresh, w.iters)
+    out["bf16_storage_value"] = w.N * w.iters / dtb
+    out["bf16_storage_rmse_vs_oracle"] = quality(pb)["rmse_vs_oracle"]
+    out["bf16_storage_kernel"] = kernel_name(api, w)
+    del pb
     Yf = device_signals(synth, w, torch.float32)
 
     def fresh32():

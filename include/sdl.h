@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SDL_ABI_VERSION 5
+#define SDL_ABI_VERSION 6
 
 /* SDL_FP64, SDL_FP32: the signals and every step in that precision (dictionary solves in FP64).
  * SDL_BF16: bfloat16 signals widened to FP32 where loaded; every step as SDL_FP32.
@@ -95,6 +95,11 @@ typedef struct sdl_stats {
   int64_t kernel_launches[8];
   int64_t proposals_accepted; /* learned path: signals whose proposal passed the test */
   int64_t fallbacks;          /* learned path: signals coded by the 2D-OMP fallback */
+  int64_t near_tie_rescores;  /* SDL_MIXED_BF16: greedy steps (summed over signals) whose pick was
+                                 decided among more than one candidate re-scored in FP32 */
+  int64_t near_tie_overflows; /* SDL_MIXED_BF16: greedy steps where some lane of the signal had its
+                                 second-largest BF16 |correlation| inside the band, so a third one of that
+                                 lane, if also inside, was not re-scored (an upper bound on such misses) */
 } sdl_stats;
 
 /* Learned support proposal network (opaque; see sdl_proposer_* below). */

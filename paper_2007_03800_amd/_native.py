@@ -26,12 +26,14 @@ class Stats(ctypes.Structure):
     _fields_ = [("early_stops", ctypes.c_int64), ("fp64_pivots", ctypes.c_int64), ("unused_atoms", ctypes.c_int64),
                 ("singular_updates", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 8),
                 ("kernel_launches", ctypes.c_int64 * 8), ("proposals_accepted", ctypes.c_int64),
-                ("fallbacks", ctypes.c_int64)]
+                ("fallbacks", ctypes.c_int64), ("near_tie_rescores", ctypes.c_int64),
+                ("near_tie_overflows", ctypes.c_int64)]
 
     def as_dict(self):
         return dict(early_stops=self.early_stops, fp64_pivots=self.fp64_pivots, unused_atoms=self.unused_atoms,
                     singular_updates=self.singular_updates, proposals_accepted=self.proposals_accepted,
-                    fallbacks=self.fallbacks,
+                    fallbacks=self.fallbacks, near_tie_rescores=self.near_tie_rescores,
+                    near_tie_overflows=self.near_tie_overflows,
                     kernel_ms={KERNEL_CLASSES[i]: self.kernel_ms[i] for i in range(8) if self.kernel_launches[i]},
                     kernel_launches={KERNEL_CLASSES[i]: self.kernel_launches[i] for i in range(8)
                                      if self.kernel_launches[i]})

@@ -547,6 +547,7 @@ hipError_t omp_fast_init_device() {
     g_num_cus = n;
     mfma_set_cus(n);
     tmod_set_cus(n);
+    tmod_bf16_set_cus(n);
   }
   return e;
 }

@@ -84,6 +84,7 @@ int get_ctx(hipStream_t st, Ctx** out) {
     if (e == hipSuccess) e = tmod_sums_init_device();
     if (e == hipSuccess) e = tmod_solve_init_device();
     if (e == hipSuccess) e = omp_fast_init_device();
+    if (e == hipSuccess) e = tmod_sums_bf16_init_device();
     if (e != hipSuccess) {
       delete c;
       return fail(SDL_E_DEVICE, "kernel attribute setup: %s", hipGetErrorString(e));
@@ -283,8 +284,14 @@ void layout(const sdl_problem* p, int nprob, size_t elem, int K, void* base, Pla
     const int na = r.n1 > r.n2 ? r.n1 : r.n2, mr = r.m1 > r.m2 ? r.m1 : r.m2;
     x.nent = na * na + mr * na;
     const size_t ae = elem == 8 ? 8 : 4;  // arithmetic element size (BF16 signals compute in FP32)
-    const int nb1 = tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2, r.s, r.n2, ae);
-    const int nb2 = tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1, r.s, r.n1, ae);
+    int nb1 = tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2, r.s, r.n2, ae);
+    int nb2 = tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1, r.s, r.n1, ae);
+    if (elem == 4 && tmod_sums_bf16_supported(r.m1, r.m2, r.n1, r.n2, r.s)) {
+      const int b1 = tmod_bf16_num_blocks(r.N, r.n1, r.m1, r.m2, r.s, r.n2);
+      const int b2 = tmod_bf16_num_blocks(r.N, r.n2, r.m2, r.m1, r.s, r.n1);
+      nb1 = nb1 > b1 ? nb1 : b1;
+      nb2 = nb2 > b2 ? nb2 : b2;
+    }
     x.nblk = nb1 > nb2 ? nb1 : nb2;
     const int rows = x.nblk > omp_fast_max_partial_rows() ? x.nblk : omp_fast_max_partial_rows();
     x.rblk = rmse_num_blocks(r.N);
@@ -461,14 +468,35 @@ TmodArgs<T> tmod_args(int side, const sdl_problem& r, const PBuf& b, const Plan&
 }
 
 // one TMOD half-step from the codes in supp/coef: standalone sums -> reduce -> solve (+ rescale)
+// Standalone sums of one side into b.part; returns the number of partial rows.  SDL_MIXED_BF16
+// runs them on the BF16 matrix cores where that kernel is compiled for the shape.
 template <typename T>
-int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, bool rescale, Launcher& L) {
+int run_sums(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, const Opt& o, Launcher& L, int* rows) {
   const TmodArgs<T> a = tmod_args<T>(side, r, b, pl);
-  const int nblk = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2, r.s, r.n2, sizeof(T))
-                              : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1, r.s, r.n1, sizeof(T));
+  bool bf16 = false;
+  if constexpr (sizeof(T) == 4) bf16 = o.prec == SDL_MIXED_BF16 && tmod_sums_bf16_supported(r.m1, r.m2, r.n1, r.n2, r.s);
+  if (bf16) {
+    *rows = side == 1 ? tmod_bf16_num_blocks(r.N, r.n1, r.m1, r.m2, r.s, r.n2)
+                      : tmod_bf16_num_blocks(r.N, r.n2, r.m2, r.m1, r.s, r.n1);
+  } else {
+    *rows = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2, r.s, r.n2, sizeof(T))
+                      : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1, r.s, r.n1, sizeof(T));
+  }
   SDL_TRY(L.begin(1));
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) {
+      HIP_TRY(launch_tmod_sums_bf16(a, b.part, L.st));
+      return L.end();
+    }
+  }
   HIP_TRY(launch_tmod_sums<T>(a, b.part, L.st));
-  SDL_TRY(L.end());
+  return L.end();
+}
+
+template <typename T>
+int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, const Opt& o, bool rescale, Launcher& L) {
+  int nblk = 0;
+  SDL_TRY(run_sums<T>(side, r, b, pl, o, L, &nblk));
   SDL_TRY(run_reduce_solve<T>(side, r, b, pl, nblk, false, -1, 0, L));
   if (rescale) {
     SDL_TRY(L.begin(6));
@@ -521,6 +549,8 @@ int finish_call(hipStream_t st, Ctx* ctx, const Plan& pl, const Opt& o, std::vec
     o.stats->fp64_pivots += (int64_t)ctr[kCtrFp64Pivot];
     o.stats->unused_atoms += (int64_t)ctr[kCtrUnusedAtoms];
     o.stats->singular_updates += (int64_t)ctr[kCtrSingular];
+    o.stats->near_tie_rescores += (int64_t)ctr[kCtrRescored];
+    o.stats->near_tie_overflows += (int64_t)ctr[kCtrTieOverflow];
     for (auto& m : marks) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[m.second], ctx->ev[m.second + 1]));
@@ -589,6 +619,7 @@ int scratch_for_device(void** out) {
     HIP_TRY(tmod_sums_init_device());
     HIP_TRY(tmod_solve_init_device());
     HIP_TRY(omp_fast_init_device());
+    HIP_TRY(tmod_sums_bf16_init_device());
     g_scratch_ptr[dev] = ptr;
   }
   *out = g_scratch_ptr[dev];
@@ -640,8 +671,8 @@ int tmod_update_impl(sdl_problem* p, int nprob, uint32_t sides, const Opt& o, hi
   }
   for (int q = 0; q < nprob; ++q) {
     SDL_TRY(run_prep<T>(p[q], pl.pb[q], L));
-    if (sides & 1u) SDL_TRY(run_update<T>(1, p[q], pl.pb[q], pl, true, L));
-    if (sides & 2u) SDL_TRY(run_update<T>(2, p[q], pl.pb[q], pl, true, L));
+    if (sides & 1u) SDL_TRY(run_update<T>(1, p[q], pl.pb[q], pl, o, true, L));
+    if (sides & 2u) SDL_TRY(run_update<T>(2, p[q], pl.pb[q], pl, o, true, L));
   }
   return finish_call(st, ctx, pl, o, marks, true);
 }
@@ -687,12 +718,8 @@ int sparse_code_sums_impl(const sdl_problem* p, int side, double* sums, const Op
     SDL_TRY(L.end());
   } else {
     SDL_TRY(run_omp<T>(r, b, o, pl, 0, L));
-    const TmodArgs<T> a = tmod_args<T>(side, r, b, pl);
-    const int nblk = side == 1 ? tmod_num_blocks_for(r.N, r.n1, r.m1, r.m2, r.s, r.n2, sizeof(T))
-                                : tmod_num_blocks_for(r.N, r.n2, r.m2, r.m1, r.s, r.n1, sizeof(T));
-    SDL_TRY(L.begin(1));
-    HIP_TRY(launch_tmod_sums<T>(a, b.part, st));
-    SDL_TRY(L.end());
+    int nblk = 0;
+    SDL_TRY(run_sums<T>(side, r, b, pl, o, L, &nblk));
     SDL_TRY(L.begin(2));
     const int nrow = launch_reduce_stage1(b.part, nblk, nent, b.stage, &src, st, &e);
     HIP_TRY(e);
@@ -740,9 +767,9 @@ int iterate_problem(sdl_problem* p, int q, int K, const Opt& o, const Plan& pl, 
     if (o.proposer) {
       SDL_TRY(run_code<T>(r, b, o, pl, L));
       SDL_TRY(run_rmse<T>(r, b, pl, q, K, L));
-      SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+      SDL_TRY(run_update<T>(1, r, b, pl, o, false, L));
       SDL_TRY(run_code<T>(r, b, o, pl, L));
-      SDL_TRY(run_update<T>(2, r, b, pl, false, L));
+      SDL_TRY(run_update<T>(2, r, b, pl, o, false, L));
     } else if (o.schedule == 0 && use_fast<T>(r, o)) {
       // Algorithm 1 with the sums (and the RMSE) computed in the sparse-coding epilogue
       const int rows = omp_fast_partial_rows(r.N, r.m1, r.m2, r.n1, r.n2, r.s);
@@ -754,12 +781,12 @@ int iterate_problem(sdl_problem* p, int q, int K, const Opt& o, const Plan& pl, 
       SDL_TRY(run_omp<T>(r, b, o, pl, 0, L));
       SDL_TRY(run_rmse<T>(r, b, pl, q, K, L));
       if (o.schedule == 0) {
-        SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+        SDL_TRY(run_update<T>(1, r, b, pl, o, false, L));
         SDL_TRY(run_omp<T>(r, b, o, pl, 0, L));
-        SDL_TRY(run_update<T>(2, r, b, pl, false, L));
+        SDL_TRY(run_update<T>(2, r, b, pl, o, false, L));
       } else {
-        SDL_TRY(run_update<T>(2, r, b, pl, true, L));
-        SDL_TRY(run_update<T>(1, r, b, pl, false, L));
+        SDL_TRY(run_update<T>(2, r, b, pl, o, true, L));
+        SDL_TRY(run_update<T>(1, r, b, pl, o, false, L));
       }
     }
   }

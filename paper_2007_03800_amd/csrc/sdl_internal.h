@@ -15,7 +15,15 @@ constexpr int kWave = 64;
 enum : int { kStatusSingular = 1, kStatusNonfinite = 2 };
 
 // Device counters (one int64-sized slot each) accumulated with integer atomics.
-enum : int { kCtrEarlyStop = 0, kCtrFp64Pivot = 1, kCtrUnusedAtoms = 2, kCtrSingular = 3, kNumCounters = 4 };
+enum : int {
+  kCtrEarlyStop = 0,
+  kCtrFp64Pivot = 1,
+  kCtrUnusedAtoms = 2,
+  kCtrSingular = 3,
+  kCtrRescored = 4,     // SDL_MIXED_BF16: signal steps with more than one candidate re-scored in FP32
+  kCtrTieOverflow = 5,  // SDL_MIXED_BF16: signal steps where a lane's second key was within the band
+  kNumCounters = 6
+};
 
 // Arguments of one sparse-coding launch over one problem.
 template <typename T>
@@ -140,6 +148,13 @@ void tmod_set_cus(int n);
 hipError_t tmod_sums_init_device();
 template <typename T>
 hipError_t launch_tmod_sums(const TmodArgs<T>& a, double* part, hipStream_t st);
+// The same sums on the BF16 matrix cores (SDL_MIXED_BF16; bfloat16 signals), for the shapes
+// compiled in tmod_bf16.hip; partial rows: tmod_bf16_num_blocks.
+bool tmod_sums_bf16_supported(int m1, int m2, int n1, int n2, int s);
+int tmod_bf16_num_blocks(int64_t N, int na, int mr, int mc, int s, int nbo);
+void tmod_bf16_set_cus(int n);
+hipError_t launch_tmod_sums_bf16(const TmodArgs<float>& a, double* part, hipStream_t st);
+hipError_t tmod_sums_bf16_init_device();
 // First stage of the fixed-order reduction of P partial rows (row stride ld): when P is
 // large, consecutive chunks of rows are summed in row order into stage (which holds
 // reduce_stage_rows(P) rows); returns the number of rows the solve kernel still has to

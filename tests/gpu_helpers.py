@@ -76,7 +76,7 @@ def compare_codes(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band, coef_rtol=Non
     return st["agree"], st["ties"], st["bad"], st["coef_err"]
 
 
-def full_size_checks(Ym, pr, s, fresh, n_each=1000, seed=11):
+def full_size_checks(Ym, pr, s, fresh, n_each=1000, seed=11, band=1e-4, **opts):
     """Checks of a problem coded at full size on the GPU (``pr``, after Algorithm 1), against
     the oracle on ``Ym`` (N, m1, m2): exactly the signal values the GPU read, in FP64.
 
@@ -98,13 +98,13 @@ def full_size_checks(Ym, pr, s, fresh, n_each=1000, seed=11):
     k = min(n_each, N)
     idx = np.unique(np.concatenate([np.arange(k), np.arange(N - k, N), rs.choice(N, k, replace=False)]))
     so, co, _ = oracle.omp(Ym[idx], e1, e2, s, p=8)
-    agree, ties, bad, err = compare_codes(Ym[idx], e1, e2, sg[idx], cg[idx], so, co, 1e-4, 1e-4)
+    agree, ties, bad, err = compare_codes(Ym[idx], e1, e2, sg[idx], cg[idx], so, co, band)
     u1 = oracle.tmod_update(1, Ym, e1, e2, sg, cg, p=8)[0]
     pu = fresh()
     pu.D1.copy_(pr.D1)
     pu.D2.copy_(pr.D2)
     pu.supp.copy_(pr.supp)
     pu.coef.copy_(pr.coef)
-    api.tmod_update(pu, sides=1)
+    api.tmod_update(pu, sides=1, **opts)
     torch.cuda.synchronize()
     return len(idx), agree, ties, bad, err, float(np.abs(pu.d1() - u1).max())

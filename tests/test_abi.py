@@ -20,7 +20,7 @@ def test_header_symbols_exported():
     lib = _native.lib()
     for n in names:
         assert hasattr(lib, n)
-    assert lib.sdl_abi_version() == 5
+    assert lib.sdl_abi_version() == 6
 
 
 def _problem(**kw):

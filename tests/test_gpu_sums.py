@@ -146,3 +146,35 @@ def test_learn_iteration_updates_match_oracle(shape, dtype, rng):
     e2 = np.abs(g2 - o2).max() / np.abs(o2).max()
     print(shape, dtype, "D1 err %.2e, D2 err %.2e" % (e1, e2))
     assert e1 <= 1e-4 and e2 <= 1e-4
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 24, 24, 12), (8, 8, 16, 16, 8), (12, 12, 20, 20, 10)],
+                         ids=lambda x: "x".join(map(str, x)))
+def test_mixed_bf16_sums_match_oracle(shape, rng):
+    """SDL_MIXED_BF16: the sums on the BF16 matrix cores (each T_k entry formed in FP32 from the
+    codes and rounded once to BF16; the signals are BF16 already; FP32 accumulation, FP64 across
+    workgroups) against the oracle's FP64 sums from the same codes.  Bar: the rounding of T_k
+    (relative 2^-9 per entry, independent across signals) enters every product of a sum once, so
+    an entry's error grows like 2^-8 sqrt(n) |product| over its n terms while the diagonal entries
+    grow like n |product|: relative to the largest entry the error is about 2^-8 / sqrt(n), which
+    for the few hundred terms per entry here is a few 1e-4; the bar is 1e-3 of the largest entry
+    (entries far below the largest carry the same absolute error, so element-wise ratios are
+    reported, not bounded)."""
+    m1, m2, n1, n2, s = shape
+    d1, d2 = rand_dicts(rng, m1, m2, n1, n2)
+    Y, _ = planted(rng, N_RAGGED, d1, d2, s, noise=0.03)
+    Y = _rounded_bf16(Y)
+    e1, e2 = rand_dicts(rng, m1, m2, n1, n2)
+    for side in (1, 2):
+        pr = api.Problem.from_math(Y, e1, e2, s, dtype=torch.bfloat16)
+        sums = api.sparse_code_sums(pr, side, mixed=True)
+        torch.cuda.synchronize()
+        A, B, r2 = api.split_sums(sums, side, pr)
+        sg, cg, rg = pr.supp.cpu().numpy(), pr.coef.cpu().double().numpy(), pr.res2.cpu().double().numpy()
+        Ao, Bo = oracle.tmod_sums(side, Y, e1, e2, sg, cg)
+        ea, eb = sums_error(A, Ao), sums_error(B, Bo)
+        na_ = np.abs(A - Ao).max() / np.abs(Ao).max()
+        nb_ = np.abs(B - Bo).max() / np.abs(Bo).max()
+        print(shape, "side %d: A err %.2e (normwise %.2e), B err %.2e (normwise %.2e)" % (side, ea, na_, eb, nb_))
+        assert na_ <= 1e-3 and nb_ <= 1e-3
+        assert abs(r2 - rg.sum()) <= 1e-9 * rg.sum()
