@@ -70,7 +70,11 @@ def _load(path=None):
         lib.sdlref_tmod_update.argtypes = [i32, i32, i32, i32, i32, i32, i64, dp, dp, dp, ip, dp, i32, dp]
         lib.sdlref_learn.argtypes = [i32, i32, i32, i32, i32, i64, i32, i32, dp, dp, dp, ip, dp, dp, dp,
                                      f64, f64, i32]
-        for f in (lib.sdlref_omp, lib.sdlref_omp_err, lib.sdlref_tmod_sums, lib.sdlref_tmod_update, lib.sdlref_learn):
+        lib.sdlref_ortho_code.argtypes = [i32, i32, i32, i64, dp, dp, dp, ip, dp, dp, i32]
+        lib.sdlref_procrustes_update.argtypes = [i32, i32, i32, i32, i64, dp, dp, dp, ip, dp, i32]
+        lib.sdlref_learn_ortho.argtypes = [i32, i32, i32, i64, i32, dp, dp, dp, ip, dp, dp, dp, i32]
+        for f in (lib.sdlref_omp, lib.sdlref_omp_err, lib.sdlref_tmod_sums, lib.sdlref_tmod_update, lib.sdlref_learn,
+                  lib.sdlref_ortho_code, lib.sdlref_procrustes_update, lib.sdlref_learn_ortho):
             f.restype = ctypes.c_int
         _libs[path] = lib
     return _libs[path]
@@ -161,6 +165,45 @@ def learn(Y, D1, D2, s, K, schedule=0, p=1, stop_rel=STOP_REL, dep_eps=DEP_EPS, 
     if st != 0 and not (allow_singular and st == -5):
         raise OracleError(st)
     return dict(D1=D1c.T.copy(), D2=D2c.T.copy(), supp=supp, coef=coef, res2=res2, rmse=rmse, status=st)
+
+
+def ortho_code(Y, D1, D2, s, p=1):
+    """Remark 1's codes for orthonormal D1 (m1 x m1), D2 (m2 x m2): X_k = T_s(D1^T Y_k D2).
+    Returns (supp, coef, res2)."""
+    Y = np.asarray(Y, np.float64)
+    N, m1, m2 = Y.shape
+    supp = np.empty((N, s), np.int32)
+    coef = np.empty((N, s), np.float64)
+    res2 = np.empty(N, np.float64)
+    _check(_load().sdlref_ortho_code(m1, m2, s, N, _ptr(_cm(Y)), _ptr(_cm(D1)), _ptr(_cm(D2)), _ptr(supp),
+                                     _ptr(coef), _ptr(res2), p))
+    return supp, coef, res2
+
+
+def procrustes_update(side, Y, D1, D2, supp, coef, p=1):
+    """Remark 1's dictionary update (orthogonal Procrustes).  Returns (D1_new, D2_new)."""
+    Y = np.asarray(Y, np.float64)
+    N, m1, m2 = Y.shape
+    s = supp.shape[1]
+    D1c, D2c = _cm(D1), _cm(D2)
+    _check(_load().sdlref_procrustes_update(side, m1, m2, s, N, _ptr(_cm(Y)), _ptr(D1c), _ptr(D2c),
+                                            _ptr(np.ascontiguousarray(supp, np.int32)),
+                                            _ptr(np.ascontiguousarray(coef, np.float64)), p))
+    return D1c.T.copy(), D2c.T.copy()
+
+
+def learn_ortho(Y, D1, D2, s, K, p=1):
+    """Algorithm 1 with Remark 1's codes and updates.  Returns dict(D1, D2, supp, coef, res2, rmse)."""
+    Y = np.asarray(Y, np.float64)
+    N, m1, m2 = Y.shape
+    D1c, D2c = _cm(D1), _cm(D2)
+    supp = np.empty((N, s), np.int32)
+    coef = np.empty((N, s), np.float64)
+    res2 = np.empty(N, np.float64)
+    rmse = np.empty(K + 1, np.float64)
+    _check(_load().sdlref_learn_ortho(m1, m2, s, N, K, _ptr(_cm(Y)), _ptr(D1c), _ptr(D2c), _ptr(supp), _ptr(coef),
+                                      _ptr(res2), _ptr(rmse), p))
+    return dict(D1=D1c.T.copy(), D2=D2c.T.copy(), supp=supp, coef=coef, res2=res2, rmse=rmse)
 
 
 def densify(supp, coef, n1, n2):

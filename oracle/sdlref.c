@@ -9,7 +9,9 @@
  *     the Kronecker dictionary D2 (x) D1 under column-major vec (Sec. I);
  *   - dictionary updates: Result 1 (D2) and Corollary 1 (D1), followed by
  *     column normalisation with the compensating rescaling of X;
- *   - iteration: Algorithm 1 (OMP, D1 update, OMP, D2 update).
+ *   - iteration: Algorithm 1 (OMP, D1 update, OMP, D2 update);
+ *   - the orthonormal variant of Remark 1: codes by hard thresholding T_s(D1^T Y_k D2),
+ *     dictionaries by orthogonal Procrustes (polar factor of the update's B sum, by SVD).
  *
  * TEST INFRASTRUCTURE ONLY: plain loops, no blocking, no BLAS.  Only the tests,
  * the smoke check and the benchmark's CPU baseline use it; it shares no code
@@ -557,6 +559,156 @@ int sdlref_learn(int m1, int m2, int n1, int n2, int s, int64_t N, int K, int sc
     }
   }
   st = sdlref_omp(0, m1, m2, n1, n2, s, N, Y, D1, D2, supp, coef, res2, stop_rel, dep_eps, p);
+  if (st) return st;
+  if (rmse_trace) rmse_trace[K] = rmse_of(res2, N, M);
+  return sticky;
+}
+
+/* ------------------------------------------------- orthonormal variant (Remark 1) */
+
+/* Remark 1, codes: with orthonormal D1 (m1 x m1) and D2 (m2 x m2), X_k = T_s(D1^T Y_k D2), the
+ * s entries of C = D1^T Y_k D2 of largest magnitude (ties: smaller atom a = i + m1*j), listed in
+ * decreasing magnitude; res2 = ||Y_k - D1 X_k D2^T||_F^2 from the explicit residual. */
+int sdlref_ortho_code(int m1, int m2, int s, int64_t N, const double* Y, const double* D1,
+                      const double* D2, int32_t* supp, double* coef, double* res2, int p) {
+  int st = check_dims(m1, m2, m1, m2, s, N);
+  if (st) return st;
+  if (!D1 || !D2 || p <= 0 || (N > 0 && (!Y || !supp || !coef))) return REF_E_INVAL;
+  const int M = m1 * m2;
+  int err = 0;
+#pragma omp parallel for schedule(static, 1) num_threads(p) reduction(| : err)
+  for (int r = 0; r < p; ++r) {
+    double* C = (double*)malloc(sizeof(double) * (size_t)(2 * M + m1 * m2));
+    char* used = (char*)malloc((size_t)M);
+    if (!C || !used) { free(C); free(used); err |= 1; continue; }
+    double* R = C + M;
+    for (int64_t k = shard_begin(N, p, r); k < shard_begin(N, p, r + 1); ++k) {
+      const double* Yk = Y + k * M;
+      for (int j = 0; j < m2; ++j)
+        for (int i = 0; i < m1; ++i) C[i + m1 * j] = bilinear(D1, D2, m1, m2, i, j, Yk);
+      memset(used, 0, (size_t)M);
+      for (int t = 0; t < s; ++t) {
+        int best = -1;
+        for (int a = 0; a < M; ++a)
+          if (!used[a] && (best < 0 || fabs(C[a]) > fabs(C[best]))) best = a;
+        used[best] = 1;
+        supp[k * s + t] = best;
+        coef[k * s + t] = C[best];
+      }
+      if (res2) {
+        memcpy(R, Yk, sizeof(double) * M);
+        for (int t = 0; t < s; ++t) {
+          const int a = supp[k * s + t], i = a % m1, j = a / m1;
+          for (int q = 0; q < m2; ++q)
+            for (int pp = 0; pp < m1; ++pp) R[pp + m1 * q] -= coef[k * s + t] * D1[pp + m1 * i] * D2[q + m2 * j];
+        }
+        double e = 0.0;
+        for (int x = 0; x < M; ++x) e += R[x] * R[x];
+        res2[k] = e;
+      }
+    }
+    free(C);
+    free(used);
+  }
+  return err ? REF_E_NOMEM : REF_OK;
+}
+
+/* Singular value decomposition of a square n x n matrix W (column-major, overwritten with
+ * U diag(sigma)) by one-sided Jacobi rotations (Hestenes): column pairs are rotated until
+ * mutually orthogonal, the rotations accumulate in V (n x n, column-major).  Returns the number
+ * of sweeps, or -1 if it did not converge in 60. */
+static int jacobi_svd(double* W, double* V, int n) {
+  for (int i = 0; i < n * n; ++i) V[i] = 0.0;
+  for (int i = 0; i < n; ++i) V[i + n * i] = 1.0;
+  for (int sweep = 1; sweep <= 60; ++sweep) {
+    int rotated = 0;
+    for (int i = 0; i < n - 1; ++i)
+      for (int j = i + 1; j < n; ++j) {
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int x = 0; x < n; ++x) {
+          a += W[x + n * i] * W[x + n * i];
+          b += W[x + n * j] * W[x + n * j];
+          g += W[x + n * i] * W[x + n * j];
+        }
+        if (fabs(g) <= 1e-15 * sqrt(a * b) || g == 0.0) continue;
+        rotated = 1;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        for (int x = 0; x < n; ++x) {
+          const double wi = W[x + n * i], wj = W[x + n * j];
+          W[x + n * i] = c * wi - sn * wj;
+          W[x + n * j] = sn * wi + c * wj;
+          const double vi = V[x + n * i], vj = V[x + n * j];
+          V[x + n * i] = c * vi - sn * vj;
+          V[x + n * j] = sn * vi + c * vj;
+        }
+      }
+    if (!rotated) return sweep;
+  }
+  return -1;
+}
+
+/* Remark 1, dictionary update: the orthonormal D1 minimising sum_k ||Y_k - D1 X_k D2^T||^2 for
+ * fixed codes maximises tr(D1^T B1) with B1 = sum_k Y_k D2 X_k^T (the B sum of Corollary 1), so it
+ * is the orthogonal Procrustes solution D1 = U V^T of B1 = U S V^T; side 2 likewise with
+ * B2 = sum_k Y_k^T D1 X_k (the B sum of Result 1).  A rank-deficient B has no unique solution:
+ * REF_E_SINGULAR, dictionary unchanged.  The codes are not rescaled (the atoms stay unit norm). */
+int sdlref_procrustes_update(int side, int m1, int m2, int s, int64_t N, const double* Y, double* D1,
+                             double* D2, const int32_t* supp, const double* coef, int p) {
+  if (side != 1 && side != 2) return REF_E_INVAL;
+  const int n = side == 1 ? m1 : m2;
+  double* A = (double*)malloc(sizeof(double) * (size_t)n * n * 4);
+  if (!A) return REF_E_NOMEM;
+  double* B = A + (size_t)n * n;
+  double* V = B + (size_t)n * n;
+  int st = sdlref_tmod_sums(side, m1, m2, m1, m2, s, N, Y, D1, D2, supp, coef, p, A, B);
+  if (st) { free(A); return st; }
+  if (jacobi_svd(B, V, n) < 0) { free(A); return REF_E_SINGULAR; }
+  double smax = 0.0, sig[4096];
+  if (n > 4096) { free(A); return REF_E_SHAPE; }
+  for (int i = 0; i < n; ++i) {
+    double v = 0.0;
+    for (int x = 0; x < n; ++x) v += B[x + n * i] * B[x + n * i];
+    sig[i] = sqrt(v);
+    if (sig[i] > smax) smax = sig[i];
+  }
+  for (int i = 0; i < n; ++i)
+    if (!(sig[i] > 1e-12 * smax)) { free(A); return REF_E_SINGULAR; }
+  double* D = side == 1 ? D1 : D2;
+  /* D = U V^T with U = B V diag(1/sigma) (the columns of the rotated B, normalised) */
+  for (int c = 0; c < n; ++c)
+    for (int x = 0; x < n; ++x) {
+      double v = 0.0;
+      for (int i = 0; i < n; ++i) v += (B[x + n * i] / sig[i]) * V[c + n * i];
+      D[x + n * c] = v;
+    }
+  free(A);
+  return REF_OK;
+}
+
+/* Algorithm 1 with the orthonormal updates of Remark 1: K iterations of (T_s codes, D1 update,
+ * T_s codes, D2 update), then final codes; rmse_trace[t] = RMSE of the codes at the start of
+ * iteration t (t = K: the final codes). */
+int sdlref_learn_ortho(int m1, int m2, int s, int64_t N, int K, const double* Y, double* D1, double* D2,
+                       int32_t* supp, double* coef, double* res2, double* rmse_trace, int p) {
+  int st = check_dims(m1, m2, m1, m2, s, N);
+  if (st) return st;
+  if (K < 0 || !res2) return REF_E_INVAL;
+  int sticky = REF_OK;
+  const int M = m1 * m2;
+  for (int it = 0; it < K; ++it) {
+    st = sdlref_ortho_code(m1, m2, s, N, Y, D1, D2, supp, coef, res2, p);
+    if (st) return st;
+    if (rmse_trace) rmse_trace[it] = rmse_of(res2, N, M);
+    st = sdlref_procrustes_update(1, m1, m2, s, N, Y, D1, D2, supp, coef, p);
+    if (st == REF_E_SINGULAR) sticky = st; else if (st) return st;
+    st = sdlref_ortho_code(m1, m2, s, N, Y, D1, D2, supp, coef, res2, p);
+    if (st) return st;
+    st = sdlref_procrustes_update(2, m1, m2, s, N, Y, D1, D2, supp, coef, p);
+    if (st == REF_E_SINGULAR) sticky = st; else if (st) return st;
+  }
+  st = sdlref_ortho_code(m1, m2, s, N, Y, D1, D2, supp, coef, res2, p);
   if (st) return st;
   if (rmse_trace) rmse_trace[K] = rmse_of(res2, N, M);
   return sticky;

@@ -65,6 +65,20 @@ int sdlref_learn(int m1, int m2, int n1, int n2, int s, int64_t N, int K, int sc
                  int32_t* supp, double* coef, double* res2, double* rmse_trace,
                  double stop_rel, double dep_eps, int p);
 
+/* Orthonormal variant (Remark 1; square dictionaries, n1 = m1, n2 = m2).
+ * Codes: X_k = T_s(D1^T Y_k D2), the s largest-magnitude entries (ties: smaller atom), listed
+ * in decreasing magnitude; res2 (may be NULL) from the explicit residual. */
+int sdlref_ortho_code(int m1, int m2, int s, int64_t N, const double* Y, const double* D1,
+                      const double* D2, int32_t* supp, double* coef, double* res2, int p);
+/* Dictionary update by orthogonal Procrustes: side 1 replaces D1 by U V^T where
+ * sum_k Y_k D2 X_k^T = U S V^T; side 2 replaces D2 likewise from sum_k Y_k^T D1 X_k.  SVD by
+ * one-sided Jacobi rotations.  -5 (dictionary kept) if that sum is rank deficient. */
+int sdlref_procrustes_update(int side, int m1, int m2, int s, int64_t N, const double* Y, double* D1,
+                             double* D2, const int32_t* supp, const double* coef, int p);
+/* Algorithm 1 with these codes and updates (K iterations, then final codes). */
+int sdlref_learn_ortho(int m1, int m2, int s, int64_t N, int K, const double* Y, double* D1, double* D2,
+                       int32_t* supp, double* coef, double* res2, double* rmse_trace, int p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,12 +60,40 @@ static int run(int m1, int m2, int n1, int n2, int s, int64_t N) {
   return bad;
 }
 
+/* the orthonormal variant (Remark 1) on square dictionaries */
+static int run_ortho(int m1, int m2, int s, int64_t N) {
+  const int64_t M = (int64_t)m1 * m2;
+  double* Y = malloc(sizeof(double) * (size_t)(M * (N > 0 ? N : 1)));
+  double* D1 = malloc(sizeof(double) * (size_t)(m1 * m1));
+  double* D2 = malloc(sizeof(double) * (size_t)(m2 * m2));
+  int32_t* supp = malloc(sizeof(int32_t) * (size_t)(s * (N > 0 ? N : 1)));
+  double* coef = malloc(sizeof(double) * (size_t)(s * (N > 0 ? N : 1)));
+  double* res2 = malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+  double trace[4];
+  int bad = 0;
+  for (int i = 0; i < m1 * m1; ++i) D1[i] = (i % (m1 + 1)) == 0 ? 1.0 : 0.0; /* identity */
+  for (int i = 0; i < m2 * m2; ++i) D2[i] = (i % (m2 + 1)) == 0 ? 1.0 : 0.0;
+  for (int64_t e = 0; e < M * N; ++e) Y[e] = unif();
+  bad |= sdlref_ortho_code(m1, m2, s, N, Y, D1, D2, supp, coef, res2, 2) != 0;
+  for (int side = 1; side <= 2; ++side) {
+    const int st = sdlref_procrustes_update(side, m1, m2, s, N, Y, D1, D2, supp, coef, 2);
+    bad |= st != 0 && st != -5;
+  }
+  const int st = sdlref_learn_ortho(m1, m2, s, N, 3, Y, D1, D2, supp, coef, res2, trace, 2);
+  bad |= st != 0 && st != -5;
+  free(Y); free(D1); free(D2); free(supp); free(coef); free(res2);
+  return bad;
+}
+
 int main(void) {
   int bad = 0;
   bad |= run(4, 3, 5, 6, 3, 17);
   bad |= run(8, 8, 12, 12, 4, 40);
   bad |= run(3, 3, 4, 4, 1, 9);
   bad |= run(5, 4, 6, 7, 2, 0);
+  bad |= run_ortho(8, 8, 8, 60);
+  bad |= run_ortho(5, 3, 4, 11);
+  bad |= run_ortho(4, 4, 2, 0);
   if (bad) {
     printf("bad status\n");
     return 1;
