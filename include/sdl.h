@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SDL_ABI_VERSION 6
+#define SDL_ABI_VERSION 7
 
 /* SDL_FP64, SDL_FP32: the signals and every step in that precision (dictionary solves in FP64).
  * SDL_BF16: bfloat16 signals widened to FP32 where loaded; every step as SDL_FP32.
@@ -67,6 +67,7 @@ enum {
 #define SDL_MAX_M 64      /* m1, m2 */
 #define SDL_MAX_N 64      /* n1, n2 */
 #define SDL_MAX_S 32      /* s */
+#define SDL_ORTHO_MAX_N 32  /* orthonormal variant (method 1): m1, m2 <= 32 and m1*m2 <= 256 */
 
 /* One dictionary problem; an array of them is one (possibly uneven) batch. */
 typedef struct sdl_problem {
@@ -145,6 +146,19 @@ typedef struct sdl_options {
                                calls that may overlap in time; its contents need not be preserved between calls.
                                Too small: SDL_E_NOMEM before any work is queued */
   size_t workspace_bytes;   /* size of workspace in bytes */
+  int32_t method;           /* 0 (default): the general method (2D-OMP codes, least-squares dictionary updates).
+                               1: the orthonormal variant of Remark 1 for square dictionaries with orthonormal
+                               columns (n1 = m1, n2 = m2; SDL_ORTHO_MAX_N): sdl_sparse_code keeps the s entries of
+                               D1^T Y_k D2 of largest magnitude (ties: smaller atom; listed in decreasing
+                               magnitude; res2 from the explicit residual); sdl_tmod_update replaces D1 by the
+                               orthogonal Procrustes solution U V^T of sum_k Y_k D2 X_k^T = U S V^T (D2 likewise from
+                               sum_k Y_k^T D1 X_k; FP64 one-sided Jacobi SVD; the codes are not rescaled; a rank-
+                               deficient sum leaves the dictionary and reports SDL_E_SINGULAR); sdl_learn iterates
+                               these as Algorithm 1 does.  Reading of the paper's printed update, which multiplies
+                               the sum by sum_k X_k X_k^T before the SVD: the polar factor of the sum alone, the
+                               minimiser of eq. (1) over orthonormal dictionaries for fixed codes.  FP32 or FP64;
+                               the caller's dictionaries must be orthonormal */
+  int32_t reserved1;        /* must be 0 */
 } sdl_options;
 
 /* Fill *o with the defaults above (prec = SDL_FP64).  Passing NULL options to the

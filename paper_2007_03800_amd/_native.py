@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("stats", ctypes.POINTER(Stats)), ("proposer", ctypes.c_void_p), ("tau", ctypes.c_double),
                 ("err2", ctypes.c_double), ("tie_band", ctypes.c_double), ("fallback_margin", ctypes.c_double),
                 ("deterministic", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("method", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class SdlError(RuntimeError):

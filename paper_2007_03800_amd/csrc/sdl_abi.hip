@@ -85,6 +85,7 @@ int get_ctx(hipStream_t st, Ctx** out) {
     if (e == hipSuccess) e = tmod_solve_init_device();
     if (e == hipSuccess) e = omp_fast_init_device();
     if (e == hipSuccess) e = tmod_sums_bf16_init_device();
+    if (e == hipSuccess) e = ortho_init_device();
     if (e != hipSuccess) {
       delete c;
       return fail(SDL_E_DEVICE, "kernel attribute setup: %s", hipGetErrorString(e));
@@ -145,6 +146,7 @@ struct Opt {
   int deterministic, reserved0;
   void* workspace;
   size_t workspace_bytes;
+  int method, reserved1;
 };
 
 Opt resolve(const sdl_options* o) {
@@ -171,6 +173,8 @@ Opt resolve(const sdl_options* o) {
   r.reserved0 = o->reserved0;
   r.workspace = o->workspace;
   r.workspace_bytes = o->workspace_bytes;
+  r.method = o->method;
+  r.reserved1 = o->reserved1;
   return r;
 }
 
@@ -201,6 +205,14 @@ int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_
   if (o.deterministic != 0 && o.deterministic != 1) return fail(SDL_E_INVAL, "deterministic must be 0 or 1");
   if (o.reserved0 != 0) return fail(SDL_E_INVAL, "reserved0 must be 0");
   if (o.workspace && o.workspace_bytes == 0) return fail(SDL_E_INVAL, "workspace given with workspace_bytes = 0");
+  if (o.method != 0 && o.method != 1) return fail(SDL_E_INVAL, "method = %d (0 or 1)", o.method);
+  if (o.reserved1 != 0) return fail(SDL_E_INVAL, "reserved1 must be 0");
+  if (o.method == 1) {
+    if (o.prec != SDL_FP64 && o.prec != SDL_FP32)
+      return fail(SDL_E_UNSUPPORTED, "the orthonormal variant runs in SDL_FP64 or SDL_FP32");
+    if (o.err2 > 0.0 || o.proposer || o.schedule != 0)
+      return fail(SDL_E_UNSUPPORTED, "the orthonormal variant has no error-driven stop, proposer or other schedule");
+  }
   if (o.err2 > 0.0 && (o.kernel == 2 || o.kernel == 3))
     return fail(SDL_E_UNSUPPORTED, "the error-driven stop runs on the generic kernel (kernel 0 or 1)");
   const size_t elem = o.prec == SDL_FP64 ? 8 : 4;
@@ -220,6 +232,9 @@ int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_
     if (!r.D1 || !r.D2) return fail(SDL_E_INVAL, "problem %d: D1/D2 is NULL", q);
     if (r.N > 0 && (!r.Y || !r.supp || !r.coef)) return fail(SDL_E_INVAL, "problem %d: Y/supp/coef is NULL", q);
     (void)need_codes_in;
+    if (o.method == 1 && !ortho_supported(r.m1, r.m2, r.n1, r.n2, r.s))
+      return fail(SDL_E_SHAPE, "problem %d: the orthonormal variant needs n1 = m1, n2 = m2, m1, m2 <= %d, m1*m2 <= 256",
+                  q, SDL_ORTHO_MAX_N);
     if (o.prec == SDL_MIXED_BF16 && !omp_mixed_supported(r.m1, r.m2, r.n1, r.n2, r.s))
       return fail(SDL_E_UNSUPPORTED, "problem %d: no SDL_MIXED_BF16 kernel for m=%dx%d n=%dx%d s=%d", q, r.m1, r.m2,
                   r.n1, r.n2, r.s);
@@ -383,7 +398,7 @@ OmpArgs<T> omp_args(const sdl_problem& r, const PBuf& b, const Opt& o, const Pla
 
 template <typename T>
 bool use_fast(const sdl_problem& r, const Opt& o) {
-  if (o.prec == SDL_MIXED_BF16) return false;
+  if (o.prec == SDL_MIXED_BF16 || o.method == 1) return false;
   if (!omp_fast_supported<T>(r.m1, r.m2, r.n1, r.n2, r.s) || o.err2 > 0.0) return false;
   return o.kernel == 2 || (o.kernel == 0 && !wave_chosen(r.m1, r.m2, r.n1, r.n2, r.s));
 }
@@ -395,6 +410,12 @@ int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, i
   OmpArgs<T> a = omp_args<T>(r, b, o, pl);
   a.sums_side = sums_side;
   a.sums_part = b.part;
+  if (o.method == 1) {
+    if (sums_side != 0) return fail(SDL_E_UNSUPPORTED, "the orthonormal variant has no fused sums");
+    SDL_TRY(L.begin(0));
+    HIP_TRY(launch_ortho_code<T>(a, L.st));
+    return L.end();
+  }
   if constexpr (sizeof(T) == 4) {
     if (o.prec == SDL_MIXED_BF16) {
       if (sums_side != 0) return fail(SDL_E_UNSUPPORTED, "SDL_MIXED_BF16 has no fused sums");
@@ -429,7 +450,7 @@ int run_prep(const sdl_problem& r, const PBuf& b, Launcher& L) {
 // rmse_q >= 0: also record the RMSE of the sweep that produced the codes for problem rmse_q
 template <typename T>
 int run_reduce_solve(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, int rows, bool with_res2,
-                     int rmse_q, int K, Launcher& L) {
+                     int rmse_q, int K, Launcher& L, int method = 0) {
   const int na = side == 1 ? r.n1 : r.n2, mr = side == 1 ? r.m1 : r.m2;
   const int nent = na * na + mr * na;
   const int ld = nent + (with_res2 ? 1 : 0);
@@ -441,6 +462,17 @@ int run_reduce_solve(int side, const sdl_problem& r, const PBuf& b, const Plan& 
     nrow = launch_reduce_stage1(b.part, rows, ld, b.stage, &src, L.st, &e);
     HIP_TRY(e);
     SDL_TRY(L.end());
+  }
+  if (method == 1) {
+    // Remark 1: the orthogonal Procrustes update from the B block of the reduced sums
+    SDL_TRY(L.begin(3));
+    if (side == 1)
+      HIP_TRY(launch_procrustes<T>(src, nrow, ld, r.n1, r.D1, (T*)b.Dc1, b.G1_64, (T*)b.G1c, pl.status, pl.counters,
+                                   L.st));
+    else
+      HIP_TRY(launch_procrustes<T>(src, nrow, ld, r.n2, r.D2, (T*)b.Dc2, b.G2_64, (T*)b.G2c, pl.status, pl.counters,
+                                   L.st));
+    return L.end();
   }
   RmseOut ro{nullptr, nullptr, 0, 0, 0.0};
   if (rmse_q >= 0) ro = RmseOut{pl.trace, pl.iter + rmse_q, rmse_q * (K + 1), nent, (double)r.N * r.m1 * r.m2};
@@ -497,8 +529,8 @@ template <typename T>
 int run_update(int side, const sdl_problem& r, const PBuf& b, const Plan& pl, const Opt& o, bool rescale, Launcher& L) {
   int nblk = 0;
   SDL_TRY(run_sums<T>(side, r, b, pl, o, L, &nblk));
-  SDL_TRY(run_reduce_solve<T>(side, r, b, pl, nblk, false, -1, 0, L));
-  if (rescale) {
+  SDL_TRY(run_reduce_solve<T>(side, r, b, pl, nblk, false, -1, 0, L, o.method));
+  if (rescale && o.method == 0) {
     SDL_TRY(L.begin(6));
     HIP_TRY(launch_rescale<T>(side, r.n1, r.s, r.N, r.supp, (T*)r.coef, b.w, L.st));
     SDL_TRY(L.end());
@@ -620,6 +652,7 @@ int scratch_for_device(void** out) {
     HIP_TRY(tmod_solve_init_device());
     HIP_TRY(omp_fast_init_device());
     HIP_TRY(tmod_sums_bf16_init_device());
+    HIP_TRY(ortho_init_device());
     g_scratch_ptr[dev] = ptr;
   }
   *out = g_scratch_ptr[dev];
@@ -847,7 +880,7 @@ std::vector<unsigned char> graph_key(const sdl_problem* p, int nprob, int K, int
   };
   put(p, sizeof(sdl_problem) * (size_t)nprob);
   const long epoch = tuning_epoch();
-  const int ints[] = {nprob, K, per, o.prec, o.schedule, o.kernel};
+  const int ints[] = {nprob, K, per, o.prec, o.schedule, o.kernel, o.method};
   const double dbl[] = {o.stop_rel, o.dep_eps, o.pivot_fp64, o.tau, o.err2, o.tie_band};
   put(ints, sizeof(ints));
   put(dbl, sizeof(dbl));
@@ -996,6 +1029,8 @@ void sdl_default_options(sdl_options* o) {
   o->reserved0 = 0;
   o->workspace = nullptr;
   o->workspace_bytes = 0;
+  o->method = 0;
+  o->reserved1 = 0;
 }
 
 int sdl_sparse_code_noalloc(const sdl_problem* p, int32_t nprob, const sdl_options* o, void* stream) {

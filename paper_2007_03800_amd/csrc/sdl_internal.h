@@ -103,6 +103,15 @@ hipError_t launch_omp_wave(const OmpArgs<T>& a, hipStream_t st);
 // form of the standalone-sums path for the shapes it is compiled for (launch_omp_wave
 // dispatches to it); no index mode, no sums epilogue.
 bool omp_quad_supported(int m1, int m2, int n1, int n2, int s);
+// Orthonormal variant (ortho.hip): hard-thresholded codes and the Procrustes update (one wave,
+// FP64 Jacobi SVD of the B block of the reduced sums, then D, its compute copy and Gram).
+bool ortho_supported(int m1, int m2, int n1, int n2, int s);
+template <typename T>
+hipError_t launch_ortho_code(const OmpArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_procrustes(const double* src, int nrow, int ld, int n, double* D, T* Dc, double* G64, T* Gc,
+                             int* status, unsigned long long* counters, hipStream_t st);
+hipError_t ortho_init_device();
 // SDL_MIXED_BF16 sparse coding (omp_mixed.hip): correlations D1^T R D2 on the BF16 matrix
 // cores every step, near-ties re-scored in FP32; shapes it is compiled for.
 bool omp_mixed_supported(int m1, int m2, int n1, int n2, int s);

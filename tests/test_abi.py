@@ -20,7 +20,7 @@ def test_header_symbols_exported():
     lib = _native.lib()
     for n in names:
         assert hasattr(lib, n)
-    assert lib.sdl_abi_version() == 6
+    assert lib.sdl_abi_version() == 7
 
 
 def _problem(**kw):
@@ -201,4 +201,25 @@ def test_noalloc_refuses_before_device_work():
     o.workspace, o.workspace_bytes = 256, 1 << 20
     assert lib.sdl_sparse_code_noalloc(arr, 1, ctypes.byref(o), None) == -1
     assert lib.sdl_sparse_code_noalloc(None, 1, None, None) == -1
+
+
+def test_orthonormal_method_validation():
+    """method 1 (Remark 1) needs square dictionaries within the limits, FP32/FP64, plain schedule."""
+    lib = _native.lib()
+    o = _native.default_options()
+    o.method = 1
+    assert _call("sparse_code", _problem(m1=8, m2=8, n1=16, n2=16, s=8), o) == -2  # n != m
+    assert _call("sparse_code", _problem(m1=40, m2=4, n1=40, n2=4, s=8), o) == -2  # m1 > 32
+    o.method = 2
+    assert _call("learn", _problem(), o) == -1
+    o = _native.default_options()
+    o.method, o.prec = 1, _native.SDL_BF16
+    assert _call("learn", _problem(m1=8, m2=8, n1=8, n2=8, s=4), o) == -7
+    o = _native.default_options()
+    o.method, o.err2 = 1, 1.0
+    assert _call("sparse_code", _problem(m1=8, m2=8, n1=8, n2=8, s=4), o) == -7
+    o = _native.default_options()
+    o.reserved1 = 3
+    assert _call("sparse_code", _problem(), o) == -1
+    assert lib.sdl_abi_version() == 7
 
