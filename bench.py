@@ -303,6 +303,41 @@ def error_driven_workload(api, oracle, synth):
             **support_agreement(supp[:nsub], s_o)}
 
 
+def ortho_workload(api, oracle, synth):
+    """Remark 1's orthonormal variant (hard-thresholded codes, orthogonal Procrustes updates) at the
+    size of the paper's m = n = 8, s = 8 timing: 128,000 FP32 signals 8x8, K = 20 iterations from
+    random orthonormal dictionaries; the sparse-coding launch timed with HIP events against its HBM
+    bytes (signals in, codes out)."""
+    import torch
+    w = synth.WORKLOADS["ortho_8x8_s8"]
+    Y = device_signals(synth, w, torch.float32)
+    e1, e2 = synth.initial_dictionaries(w)
+
+    def fresh():
+        return api.Problem(Y, torch.from_numpy(e1.T.copy()).cuda(), torch.from_numpy(e2.T.copy()).cuda(), w.s)
+
+    pr, trace, dt = timed_learn(api, fresh, w.iters, method=1)
+    st = api.new_stats()
+    p2 = fresh()
+    for _ in range(5):
+        api.sparse_code(p2, method=1, timing=1, stats=st)
+    torch.cuda.synchronize()
+    d = st.as_dict()
+    ms = d["kernel_ms"]["sparse_code"] / d["kernel_launches"]["sparse_code"]
+    nsub = 5000
+    Ysub = synth.signals(w, 0, nsub)
+    s_o, _, r_o = oracle.ortho_code(Ysub, pr.d1(), pr.d2(), w.s, p=min(16, os.cpu_count() or 1))
+    r_g = pr.res2[:nsub].double().cpu().numpy()
+    nbytes = w.N * (4 * w.m1 * w.m2 + 8 * w.s + 4)
+    return {"workload": w.name, "N": w.N, "steps": w.iters, "value": w.N * w.iters / dt,
+            "unit": "signals/s per iteration", "ms_per_step": dt / w.iters * 1e3,
+            "rmse_first": float(trace[0][0]), "rmse_final": float(trace[0][-1]),
+            "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
+            **support_agreement(pr.supp[:nsub].cpu().numpy(), s_o),
+            "code_kernel_ms": ms, "code_hbm_gbs": nbytes / (ms * 1e-3) / 1e9,
+            "code_kernel": "ortho_code_kernel<float> (hard thresholding, 16 lanes per signal)"}
+
+
 def uneven_workload(api, oracle, synth):
     """The uneven batch: four problems of different shapes and sizes (370k signals in all)
     learned together in one call, K = 10."""
@@ -386,6 +421,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-error-driven", action="store_true")
+    ap.add_argument("--no-ortho", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one elementwise FP32 copy of MIB MiB (reads and writes MIB MiB): "
                          "the reference dispatch that scales hardware byte counters")
@@ -481,6 +517,7 @@ def main():
     mixed = None if args.no_mixed else mixed_workload(api, oracle, synth)
     uneven = None if args.no_uneven else uneven_workload(api, oracle, synth)
     errdriven = None if args.no_error_driven else error_driven_workload(api, oracle, synth)
+    ortho = None if args.no_ortho else ortho_workload(api, oracle, synth)
 
     symbol = kernel_symbol(w, tuned)
     out = {
@@ -522,6 +559,7 @@ def main():
         "mixed_precision": mixed,
         "uneven_batch": uneven,
         "error_driven": errdriven,
+        "orthonormal": ortho,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

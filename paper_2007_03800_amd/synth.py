@@ -12,7 +12,8 @@ both the FP64 CPU oracle and the GPU library are fed from here, and nothing here
 depends on either of them.
 
 Streams: 0 true D1, 1 true D2, 2 supports, 3 coefficients, 4 noise,
-5 initial D1, 6 initial D2, 7 network initialisation, 8 batch order.
+5 initial D1, 6 initial D2, 7 network initialisation, 8 batch order,
+9 image content, 10 image noise, 11 training-patch choice.
 
 Array conventions (numpy, "math shape"): Y is (N, m1, m2) with Y[k, i, j] the
 pixel (i, j) of signal k; D1 is (m1, n1); D2 is (m2, n2); a code is a list of s
@@ -64,6 +65,14 @@ def unit_norm_dictionary(seed: int, stream: int, m: int, n: int) -> np.ndarray:
     return d
 
 
+def orthonormal_dictionary(seed: int, stream: int, m: int) -> np.ndarray:
+    """(m, m) orthogonal matrix: the Q factor of an i.i.d. N(0,1) matrix (counter = p + m*i), with
+    the signs of R's diagonal moved into Q so that the draw is uniform (Haar) and unique."""
+    g = normal(seed, stream, np.arange(m * m)).reshape(m, m).T
+    q, r = np.linalg.qr(g)
+    return q * np.sign(np.diag(r))
+
+
 def random_supports(seed: int, k0: int, k1: int, n_atoms: int, s: int) -> np.ndarray:
     """s distinct atoms per signal, uniform over all size-s subsets (Floyd's sampling).
 
@@ -111,6 +120,7 @@ class Workload:
     coef_kind: str
     seed: int
     iters: int
+    orthonormal: bool = False  # square dictionaries with orthonormal columns (Remark 1's variant)
 
     @property
     def n_atoms(self) -> int:
@@ -142,6 +152,8 @@ WORKLOADS = {
     "uneven_p4_32x24_n48x36_s20": Workload("uneven_p4_32x24_n48x36_s20", 32, 24, 48, 36, 20, 20_000, 30.0,
                                            "normal", 1003, 10),
     "learned_8x8_n16_s8": Workload("learned_8x8_n16_s8", 8, 8, 16, 16, 8, 1_500_000, 30.0, "normal", 1004, 0),
+    # Remark 1's orthonormal variant at the size of the paper's m = n = 8, s = 8 timing (128,000 patches)
+    "ortho_8x8_s8": Workload("ortho_8x8_s8", 8, 8, 8, 8, 8, 128_000, 30.0, "normal", 1005, 20, True),
 }
 UNEVEN_BATCH = ["uneven_p1_8x8_n16_s6", "uneven_p2_12x12_n20_s10", "uneven_p3_16x16_n32_s16",
                 "uneven_p4_32x24_n48x36_s20"]
@@ -154,14 +166,19 @@ def _problem_seed(w: Workload) -> int:
     return w.seed
 
 
-def true_dictionaries(w: Workload):
+def _dictionaries(w: Workload, s1: int, s2: int):
     sd = _problem_seed(w)
-    return unit_norm_dictionary(sd, 0, w.m1, w.n1), unit_norm_dictionary(sd, 1, w.m2, w.n2)
+    if w.orthonormal:
+        return orthonormal_dictionary(sd, s1, w.m1), orthonormal_dictionary(sd, s2, w.m2)
+    return unit_norm_dictionary(sd, s1, w.m1, w.n1), unit_norm_dictionary(sd, s2, w.m2, w.n2)
+
+
+def true_dictionaries(w: Workload):
+    return _dictionaries(w, 0, 1)
 
 
 def initial_dictionaries(w: Workload):
-    sd = _problem_seed(w)
-    return unit_norm_dictionary(sd, 5, w.m1, w.n1), unit_norm_dictionary(sd, 6, w.m2, w.n2)
+    return _dictionaries(w, 5, 6)
 
 
 def planted_codes(w: Workload, k0: int, k1: int):
@@ -207,3 +224,40 @@ def to_colmajor(a: np.ndarray) -> np.ndarray:
 
 def from_colmajor(a: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(np.swapaxes(a, -1, -2))
+
+
+def synthetic_image(seed: int, H: int = 512, W: int = 512) -> np.ndarray:
+    """A (H, W) grey-level image in [0, 255] standing in for the paper's 512 x 512 test images:
+    a smooth background (a few low-frequency cosines), 24 axis-aligned rectangles and 12 discs of
+    random intensity, and a band of fine stripes, so that patches have flat areas, edges and texture."""
+    u = lambda n, off: uniform(seed, 9, np.arange(off, off + n))
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    img = np.full((H, W), 110.0)
+    c = u(12, 0)
+    for k in range(3):
+        fy, fx, ph = 1 + 3 * c[4 * k], 1 + 3 * c[4 * k + 1], 2 * math.pi * c[4 * k + 2]
+        img += 25.0 * (c[4 * k + 3] - 0.5) * 2 * np.cos(2 * math.pi * (fy * yy / H + fx * xx / W) + ph)
+    r = u(24 * 5, 100)
+    for k in range(24):
+        y0, x0 = int(r[5 * k] * H * 0.9), int(r[5 * k + 1] * W * 0.9)
+        h, w = int(8 + r[5 * k + 2] * H * 0.25), int(8 + r[5 * k + 3] * W * 0.25)
+        img[y0:y0 + h, x0:x0 + w] = 30.0 + 200.0 * r[5 * k + 4]
+    d = u(12 * 4, 1000)
+    for k in range(12):
+        cy, cx, rad = d[4 * k] * H, d[4 * k + 1] * W, 6 + d[4 * k + 2] * H * 0.08
+        img[(yy - cy) ** 2 + (xx - cx) ** 2 <= rad ** 2] = 20.0 + 215.0 * d[4 * k + 3]
+    band = (yy > 0.70 * H) & (yy < 0.78 * H)
+    img[band] += 30.0 * np.sign(np.sin(2 * math.pi * xx[band] / 6.0))
+    return np.clip(img, 0.0, 255.0)
+
+
+def noisy_image(img: np.ndarray, seed: int, sigma: float) -> np.ndarray:
+    """img + sigma * N(0, 1) i.i.d. per pixel (stream 10)."""
+    return img + sigma * normal(seed, 10, np.arange(img.size)).reshape(img.shape)
+
+
+def training_patch_index(seed: int, n_patches: int, count: int) -> np.ndarray:
+    """count distinct patch indices out of n_patches, uniformly (stream 11), sorted."""
+    u = uniform(seed, 11, np.arange(4 * count))
+    idx = np.unique(np.floor(u * n_patches).astype(np.int64))[:count]
+    return np.sort(idx)

@@ -38,3 +38,11 @@ def test_snr_matches_definition():
     clean = np.einsum("kt,pkt,qkt->kpq", coef, d1[:, supp % 16], d2[:, supp // 16])
     snr = 10 * np.log10(np.sum(clean ** 2) / np.sum((y - clean) ** 2))
     assert abs(snr - w.snr_db) < 0.3
+
+
+def test_orthonormal_workload_dictionaries():
+    w = synth.WORKLOADS["ortho_8x8_s8"]
+    for d in (*synth.true_dictionaries(w), *synth.initial_dictionaries(w)):
+        np.testing.assert_allclose(d.T @ d, np.eye(d.shape[0]), atol=1e-14)
+    a, b = synth.true_dictionaries(w)
+    assert np.abs(a - b).max() > 0.1  # different streams
