@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SDL_ABI_VERSION 7
+#define SDL_ABI_VERSION 8
 
 /* SDL_FP64, SDL_FP32: the signals and every step in that precision (dictionary solves in FP64).
  * SDL_BF16: bfloat16 signals widened to FP32 where loaded; every step as SDL_FP32.
@@ -229,6 +229,22 @@ int sdl_workspace_bytes(const sdl_problem* p, int32_t nprob, int32_t call, int32
 /* 1 if SDL_MIXED_BF16 has a kernel for this shape (signal rows and columns and atom counts
  * multiples of 4 within the compiled set), else 0. */
 int sdl_mixed_supported(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s);
+
+/* Denoising driver of the experiments in Sec. IV (overlapping patches of a noisy image coded by the
+ * error-driven 2D-OMP, then put back together).  Step 1: all (H-m1+1)(W-m2+1) overlapping m1 x m2
+ * patches of an H x W image (row-major, pixel (y, x) at y*W + x), stride 1, as signals in the layout
+ * above: patch k = r*(W-m2+1) + c holds pixel (r+i, c+j) at its (i, j).  prec: SDL_FP32 or SDL_FP64,
+ * the element type of both arrays (device pointers; patches holds (H-m1+1)(W-m2+1)*m1*m2 elements).
+ * Asynchronous on `stream`.  Step 2 is sdl_sparse_code with options->err2 (eps^2) and s as the cap. */
+int sdl_image_to_patches(const void* image, int32_t H, int32_t W, int32_t m1, int32_t m2, int32_t prec,
+                         void* patches, void* stream);
+/* Step 3: the H x W image rebuilt from the codes of those patches (p: m1, m2, n1, n2, s, D1, D2, supp,
+ * coef and N = (H-m1+1)(W-m2+1); Y and res2 unused): every pixel is the plain average, over the patches
+ * covering it, of D1 X_k D2^T at that pixel (a reading: the paper does not say how overlapping
+ * estimates are combined).  options->prec (SDL_FP32 or SDL_FP64) is the type of coef and image.
+ * Asynchronous on `stream`. */
+int sdl_patches_to_image(const sdl_problem* p, int32_t H, int32_t W, const sdl_options* o, void* image,
+                         void* stream);
 
 /* Autotuner (no counterpart in the paper; a property of this GPU implementation):
  * for every FP32 problem whose shape has register-resident kernel variants

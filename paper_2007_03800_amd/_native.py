@@ -102,6 +102,10 @@ def lib():
         L.sdl_sparse_code_sums.argtypes = [P, i32, vp, ctypes.POINTER(Options), vp]
         L.sdl_workspace_bytes.argtypes = [P, i32, i32, i32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]
         L.sdl_mixed_supported.argtypes = [i32] * 5
+        L.sdl_image_to_patches.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
+        L.sdl_image_to_patches.restype = ctypes.c_int
+        L.sdl_patches_to_image.argtypes = [P, i32, i32, ctypes.POINTER(Options), vp, vp]
+        L.sdl_patches_to_image.restype = ctypes.c_int
         L.sdl_sparse_code_noalloc.argtypes = [P, i32, ctypes.POINTER(Options), vp]
         L.sdl_sparse_code_noalloc.restype = ctypes.c_int
         for f in (L.sdl_proposer_save, L.sdl_proposer_load, L.sdl_sparse_code_sums, L.sdl_workspace_bytes,

@@ -157,6 +157,46 @@ def workspace_bytes(problems: Problem | Sequence[Problem], call: str = "learn", 
     return n.value
 
 
+def image_to_patches(image: torch.Tensor, m1: int, m2: int, stream=None) -> torch.Tensor:
+    """All overlapping m1 x m2 patches (stride 1) of a row-major (H, W) float32/float64 device image,
+    as signals in ABI layout: (N, m2, m1) with N = (H - m1 + 1)(W - m2 + 1)."""
+    if image.dim() != 2 or not image.is_contiguous():
+        raise ValueError("image must be a contiguous (H, W) tensor")
+    H, W = image.shape
+    prec = _DT[image.dtype]
+    out = torch.empty(((H - m1 + 1) * (W - m2 + 1), m2, m1), dtype=image.dtype, device=image.device)
+    _native.check(_native.lib().sdl_image_to_patches(ctypes.c_void_p(image.data_ptr()), H, W, m1, m2, prec,
+                                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def patches_to_image(problem: Problem, H: int, W: int, stream=None, **opts) -> torch.Tensor:
+    """The (H, W) image rebuilt from the problem's codes of those patches (plain average of the
+    overlapping estimates)."""
+    out = torch.empty((H, W), dtype=problem.coef.dtype, device=problem.coef.device)
+    o = _options([problem], None, **opts)
+    _native.check(_native.lib().sdl_patches_to_image(_array([problem]), H, W, ctypes.byref(o),
+                                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def denoise(noisy: torch.Tensor, D1: torch.Tensor, D2: torch.Tensor, sigma: float, s_cap: int | None = None,
+            c_eps: float = 1.15, stream=None, stats=None, **opts):
+    """The denoising experiment of Sec. IV on one image: every overlapping patch of ``noisy`` (H, W) is
+    coded by the error-driven 2D-OMP with eps = c_eps sigma sqrt(m1 m2) and at most s_cap atoms (default
+    m1 m2 / 2), and the image is rebuilt from the codes.  D1 (n1, m1), D2 (n2, m2) are FP64 device
+    dictionaries in ABI layout.  Returns (denoised image, the coded problem)."""
+    n1, m1 = D1.shape
+    n2, m2 = D2.shape
+    P = image_to_patches(noisy, m1, m2, stream=stream)
+    s = s_cap if s_cap is not None else m1 * m2 // 2
+    pr = Problem(P, D1, D2, s)
+    err2 = (c_eps * sigma) ** 2 * m1 * m2
+    sparse_code(pr, stream=stream, stats=stats, err2=err2, **opts)
+    H, W = noisy.shape
+    return patches_to_image(pr, H, W, stream=stream), pr
+
+
 def mixed_supported(m1, m2, n1, n2, s) -> bool:
     return bool(_native.lib().sdl_mixed_supported(m1, m2, n1, n2, s))
 

@@ -1003,6 +1003,23 @@ int time_median(hipStream_t st, int reps, double* out, F f) {
   return SDL_OK;
 }
 
+template <typename T>
+int patches_to_image_impl(const sdl_problem* p, int H, int W, const Opt& o, void* image, hipStream_t st) {
+  Ctx* ctx;
+  SDL_TRY(get_ctx(st, &ctx));
+  Plan pl;
+  layout(p, 1, sizeof(T), 0, nullptr, &pl);
+  void* wsb = nullptr;
+  SDL_TRY(acquire_ws(ctx, o, pl.bytes, st, &wsb));
+  layout(p, 1, sizeof(T), 0, wsb, &pl);
+  std::vector<std::pair<int, int>> marks;
+  Launcher L{st, false, ctx, &marks};
+  SDL_TRY(run_prep<T>(p[0], pl.pb[0], L));
+  HIP_TRY(launch_patches_to_image<T>(p->supp, (const T*)p->coef, (const T*)pl.pb[0].Dc1, (const T*)pl.pb[0].Dc2, H, W,
+                                     p->m1, p->m2, p->n1, p->s, (T*)image, st));
+  return SDL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1057,6 +1074,38 @@ int sdl_sparse_code_sums(const sdl_problem* p, int32_t side, double* sums, const
   hipStream_t st = (hipStream_t)stream;
   return opt.prec == SDL_FP64 ? sparse_code_sums_impl<double>(p, side, sums, opt, st)
                               : sparse_code_sums_impl<float>(p, side, sums, opt, st);
+}
+
+int sdl_image_to_patches(const void* image, int32_t H, int32_t W, int32_t m1, int32_t m2, int32_t prec,
+                         void* patches, void* stream) {
+  g_err.clear();
+  if (prec != SDL_FP32 && prec != SDL_FP64) return fail(SDL_E_INVAL, "prec must be SDL_FP32 or SDL_FP64");
+  if (m1 <= 0 || m2 <= 0 || m1 > SDL_MAX_M || m2 > SDL_MAX_M || H < m1 || W < m2)
+    return fail(SDL_E_SHAPE, "need 0 < m1 <= H, 0 < m2 <= W and m1, m2 <= %d", SDL_MAX_M);
+  if (!image || !patches) return fail(SDL_E_INVAL, "NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == SDL_FP64)
+    HIP_TRY(launch_image_to_patches<double>((const double*)image, H, W, m1, m2, (double*)patches, st));
+  else
+    HIP_TRY(launch_image_to_patches<float>((const float*)image, H, W, m1, m2, (float*)patches, st));
+  return SDL_OK;
+}
+
+int sdl_patches_to_image(const sdl_problem* p, int32_t H, int32_t W, const sdl_options* o, void* image,
+                         void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  if (!p || !image) return fail(SDL_E_INVAL, "NULL pointer");
+  if (opt.prec != SDL_FP32 && opt.prec != SDL_FP64) return fail(SDL_E_INVAL, "prec must be SDL_FP32 or SDL_FP64");
+  sdl_problem q = *p;
+  q.Y = q.Y ? q.Y : image;  // signals are not read
+  SDL_TRY(validate(&q, 1, opt, false));
+  if (H < p->m1 || W < p->m2 || (int64_t)(H - p->m1 + 1) * (W - p->m2 + 1) != p->N)
+    return fail(SDL_E_SHAPE, "N = %lld is not (H - m1 + 1)(W - m2 + 1) for H = %d, W = %d", (long long)p->N, H, W);
+  SDL_TRY(check_workspace(&q, 1, 0, opt));
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? patches_to_image_impl<double>(&q, H, W, opt, image, st)
+                              : patches_to_image_impl<float>(&q, H, W, opt, image, st);
 }
 
 int sdl_mixed_supported(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s) {

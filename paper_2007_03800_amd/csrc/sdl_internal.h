@@ -211,5 +211,12 @@ template <typename T>
 hipError_t launch_check_finite(const T* x, int64_t n, int* status, hipStream_t st);
 hipError_t launch_check_finite_bf16(const uint16_t* x, int64_t n, int* status, hipStream_t st);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
+// Denoising driver (denoise.hip): overlapping patches of a row-major image as column-major
+// signals, and the image rebuilt as the average of the coded patches covering each pixel.
+template <typename T>
+hipError_t launch_image_to_patches(const T* img, int H, int W, int m1, int m2, T* out, hipStream_t st);
+template <typename T>
+hipError_t launch_patches_to_image(const int32_t* supp, const T* coef, const T* D1, const T* D2, int H, int W, int m1,
+                                   int m2, int n1, int s, T* img, hipStream_t st);
 
 }  // namespace sdl

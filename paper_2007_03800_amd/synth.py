@@ -261,3 +261,13 @@ def training_patch_index(seed: int, n_patches: int, count: int) -> np.ndarray:
     u = uniform(seed, 11, np.arange(4 * count))
     idx = np.unique(np.floor(u * n_patches).astype(np.int64))[:count]
     return np.sort(idx)
+
+
+def overcomplete_dct(m: int, n: int) -> np.ndarray:
+    """(m, n) dictionary of sampled cosines, column k = cos(pi (i + 1/2) k / n), i = 0..m-1, scaled
+    to unit norm: the usual starting dictionary of patch-based dictionary learning (n = m gives the
+    orthonormal DCT-II basis)."""
+    i = np.arange(m)[:, None] + 0.5
+    k = np.arange(n)[None, :]
+    d = np.cos(np.pi * i * k / n)
+    return d / np.linalg.norm(d, axis=0)

@@ -20,7 +20,7 @@ def test_header_symbols_exported():
     lib = _native.lib()
     for n in names:
         assert hasattr(lib, n)
-    assert lib.sdl_abi_version() == 7
+    assert lib.sdl_abi_version() == 8
 
 
 def _problem(**kw):
@@ -221,5 +221,23 @@ def test_orthonormal_method_validation():
     o = _native.default_options()
     o.reserved1 = 3
     assert _call("sparse_code", _problem(), o) == -1
-    assert lib.sdl_abi_version() == 7
+    assert lib.sdl_abi_version() == 8
 
+
+
+def test_denoise_driver_validation():
+    lib = _native.lib()
+    o = _native.default_options()
+    o.prec = 1  # SDL_FP32
+    # patch extraction: element type, patch larger than the image, NULL pointers
+    assert lib.sdl_image_to_patches(ctypes.c_void_p(1), 16, 16, 8, 8, 2, ctypes.c_void_p(2), None) == -1
+    assert lib.sdl_image_to_patches(ctypes.c_void_p(1), 7, 16, 8, 8, 1, ctypes.c_void_p(2), None) == -2
+    assert lib.sdl_image_to_patches(ctypes.c_void_p(1), 16, 16, 0, 8, 1, ctypes.c_void_p(2), None) == -2
+    assert lib.sdl_image_to_patches(None, 16, 16, 8, 8, 1, ctypes.c_void_p(2), None) == -1
+    # reconstruction: N must be the number of overlapping patches of an H x W image
+    arr = (_native.Problem * 1)(_problem(N=81, Y=None))
+    assert lib.sdl_patches_to_image(arr, 16, 16, ctypes.byref(o), None, None) == -1
+    assert lib.sdl_patches_to_image(arr, 16, 17, ctypes.byref(o), ctypes.c_void_p(7), None) == -2
+    assert lib.sdl_patches_to_image(arr, 7, 16, ctypes.byref(o), ctypes.c_void_p(7), None) == -2
+    o.prec = 2  # SDL_BF16 codes are FP32; the image is FP32 or FP64
+    assert lib.sdl_patches_to_image(arr, 16, 16, ctypes.byref(o), ctypes.c_void_p(7), None) == -1
