@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SDL_ABI_VERSION 8
+#define SDL_ABI_VERSION 9
 
 /* SDL_FP64, SDL_FP32: the signals and every step in that precision (dictionary solves in FP64).
  * SDL_BF16: bfloat16 signals widened to FP32 where loaded; every step as SDL_FP32.
@@ -245,6 +245,43 @@ int sdl_image_to_patches(const void* image, int32_t H, int32_t W, int32_t m1, in
  * Asynchronous on `stream`. */
 int sdl_patches_to_image(const sdl_problem* p, int32_t H, int32_t W, const sdl_options* o, void* image,
                          void* stream);
+
+/* n-dimensional signals (Remark 3).  A signal is a tensor Y_k of m[0] x ... x m[nmodes-1] entries,
+ * stored first index fastest; the dictionary is separable over the modes, Y_k ~ X_k x_1 D_1 ... x_n
+ * D_n with D_d (m[d] x n[d], column-major FP64, caller-owned, updated in place), so that it acts on
+ * vec(Y_k) as D_n (x) ... (x) D_1 and atom a = i_0 + n[0] (i_1 + n[1] (i_2 + ...)).  Entries of m,
+ * n and D beyond nmodes are ignored.  supp/coef/res2 as for sdl_problem (coef and res2 in the
+ * element type of Y). */
+#define SDL_TENSOR_MAX_MODES 4
+#define SDL_TENSOR_MAX_ELEMS 4096 /* largest prod m[d] and prod n[d] */
+typedef struct {
+  int32_t nmodes; /* 2 .. SDL_TENSOR_MAX_MODES */
+  int32_t s;      /* atoms per signal (cap) */
+  int32_t m[SDL_TENSOR_MAX_MODES];
+  int32_t n[SDL_TENSOR_MAX_MODES];
+  int64_t N;
+  const void* Y;
+  double* D[SDL_TENSOR_MAX_MODES];
+  int32_t* supp;
+  void* coef;
+  void* res2; /* optional for sdl_tensor_sparse_code, required by sdl_tensor_learn */
+} sdl_tensor_problem;
+/* Sparse coding of every signal by OMP on the Kronecker dictionary (Sec. II's equivalence, mode by
+ * mode), with the stopping rules of sdl_sparse_code (stop_rel, dep_eps, pivot_fp64, err2).
+ * options->prec: SDL_FP64 or SDL_FP32; kernel, method, schedule and proposer must be 0 and
+ * workspace NULL (SDL_E_UNSUPPORTED otherwise).  Asynchronous unless stats is set. */
+int sdl_tensor_sparse_code(const sdl_tensor_problem* p, const sdl_options* o, void* stream);
+/* The update of mode `mode` (1..nmodes) from the codes in supp/coef (Remark 3: Corollary 1 with the
+ * other modes' Kronecker product fixed): D_mode solves D A = B with A = sum_k W_k W_k^T,
+ * B = sum_k Y_k(mode) W_k^T, W_k the mode-`mode` matricisation of X_k multiplied along every other
+ * mode by its dictionary; atoms no code uses are kept; columns are normalised and the codes
+ * rescaled.  SDL_E_SINGULAR leaves D unchanged.  Synchronous. */
+int sdl_tensor_update(const sdl_tensor_problem* p, int32_t mode, const sdl_options* o, void* stream);
+/* Algorithm 1 with one sweep per mode, K iterations: for each mode, sparse coding then that mode's
+ * update; then a final sparse coding.  rmse_trace (host, optional, K + 1 values): the RMSE of each
+ * iteration's first sweep and of the final one.  Synchronous. */
+int sdl_tensor_learn(const sdl_tensor_problem* p, int32_t K, double* rmse_trace, const sdl_options* o,
+                     void* stream);
 
 /* Autotuner (no counterpart in the paper; a property of this GPU implementation):
  * for every FP32 problem whose shape has register-resident kernel variants

@@ -22,6 +22,16 @@ class Problem(ctypes.Structure):
                 ("supp", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("res2", ctypes.c_void_p)]
 
 
+TENSOR_MAX_MODES = 4
+
+
+class TensorProblem(ctypes.Structure):
+    _fields_ = [("nmodes", ctypes.c_int32), ("s", ctypes.c_int32), ("m", ctypes.c_int32 * TENSOR_MAX_MODES),
+                ("n", ctypes.c_int32 * TENSOR_MAX_MODES), ("N", ctypes.c_int64), ("Y", ctypes.c_void_p),
+                ("D", ctypes.c_void_p * TENSOR_MAX_MODES), ("supp", ctypes.c_void_p), ("coef", ctypes.c_void_p),
+                ("res2", ctypes.c_void_p)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("early_stops", ctypes.c_int64), ("fp64_pivots", ctypes.c_int64), ("unused_atoms", ctypes.c_int64),
                 ("singular_updates", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 8),
@@ -102,6 +112,12 @@ def lib():
         L.sdl_sparse_code_sums.argtypes = [P, i32, vp, ctypes.POINTER(Options), vp]
         L.sdl_workspace_bytes.argtypes = [P, i32, i32, i32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]
         L.sdl_mixed_supported.argtypes = [i32] * 5
+        TP = ctypes.POINTER(TensorProblem)
+        L.sdl_tensor_sparse_code.argtypes = [TP, ctypes.POINTER(Options), ctypes.c_void_p]
+        L.sdl_tensor_update.argtypes = [TP, ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p]
+        L.sdl_tensor_learn.argtypes = [TP, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(Options), ctypes.c_void_p]
+        for f in (L.sdl_tensor_sparse_code, L.sdl_tensor_update, L.sdl_tensor_learn):
+            f.restype = ctypes.c_int
         L.sdl_image_to_patches.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
         L.sdl_image_to_patches.restype = ctypes.c_int
         L.sdl_patches_to_image.argtypes = [P, i32, i32, ctypes.POINTER(Options), vp, vp]

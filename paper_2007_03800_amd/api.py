@@ -16,6 +16,7 @@ from __future__ import annotations
 import ctypes
 from typing import Sequence
 
+import numpy as np
 import torch
 
 from . import _native
@@ -195,6 +196,88 @@ def denoise(noisy: torch.Tensor, D1: torch.Tensor, D2: torch.Tensor, sigma: floa
     sparse_code(pr, stream=stream, stats=stats, err2=err2, **opts)
     H, W = noisy.shape
     return patches_to_image(pr, H, W, stream=stream), pr
+
+
+class TensorProblem:
+    """n-dimensional signals (Remark 3) in ABI layout: Y (N, m_n, ..., m_1) contiguous, i.e. each
+    signal stored first index fastest; dictionaries D_d as FP64 (n_d, m_d) tensors (column-major
+    m_d x n_d)."""
+
+    def __init__(self, Y: torch.Tensor, Ds, s: int, with_res2: bool = True):
+        nm = len(Ds)
+        if not 2 <= nm <= _native.TENSOR_MAX_MODES or Y.dim() != nm + 1:
+            raise ValueError("Y must be (N, m_n, ..., m_1) with 2..4 modes, one dictionary per mode")
+        if Y.dtype not in (torch.float64, torch.float32) or not Y.is_contiguous():
+            raise ValueError("Y must be a contiguous float64 or float32 tensor")
+        self.m = [int(x) for x in reversed(Y.shape[1:])]
+        self.n = [int(D.shape[0]) for D in Ds]
+        for d, D in enumerate(Ds):
+            if D.dtype != torch.float64 or not D.is_contiguous() or D.shape[1] != self.m[d]:
+                raise ValueError("dictionary %d must be a contiguous float64 (n_d, m_d) tensor" % (d + 1))
+        self.N, self.s, self.Y, self.Ds = int(Y.shape[0]), int(s), Y, list(Ds)
+        dev = Y.device
+        self.supp = torch.empty((self.N, self.s), dtype=torch.int32, device=dev)
+        self.coef = torch.empty((self.N, self.s), dtype=Y.dtype, device=dev)
+        self.res2 = torch.empty(self.N, dtype=Y.dtype, device=dev) if with_res2 else None
+
+    @classmethod
+    def from_math(cls, Y, Ds, s, dtype=torch.float64, device="cuda"):
+        """Y (N, m_1, ..., m_n), D_d (m_d, n_d) (numpy or torch) -> ABI-layout device buffers."""
+        Y = torch.as_tensor(Y)
+        nm = Y.dim() - 1
+        Yc = Y.to(device=device, dtype=dtype).permute(0, *range(nm, 0, -1)).contiguous()
+        return cls(Yc, [torch.as_tensor(D).to(device=device, dtype=torch.float64).t().contiguous() for D in Ds], s)
+
+    def dicts(self):
+        """The dictionaries in math shape (m_d, n_d), on the host."""
+        return [D.t().cpu().numpy() for D in self.Ds]
+
+    def struct(self) -> _native.TensorProblem:
+        t = _native.TensorProblem()
+        t.nmodes, t.s, t.N = len(self.Ds), self.s, self.N
+        for d in range(len(self.Ds)):
+            t.m[d], t.n[d] = self.m[d], self.n[d]
+            t.D[d] = self.Ds[d].data_ptr()
+        t.Y = self.Y.data_ptr()
+        t.supp, t.coef = self.supp.data_ptr(), self.coef.data_ptr()
+        t.res2 = self.res2.data_ptr() if self.res2 is not None else None
+        return t
+
+
+def _tensor_options(problem: TensorProblem, stats=None, **kw):
+    o = _native.default_options()
+    o.prec = _DT[problem.Y.dtype]
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, v)
+    if stats is not None:
+        o.stats = ctypes.pointer(stats)
+    return o
+
+
+def tensor_sparse_code(problem: TensorProblem, stream=None, stats=None, **opts):
+    o = _tensor_options(problem, stats, **opts)
+    t = problem.struct()
+    _native.check(_native.lib().sdl_tensor_sparse_code(ctypes.byref(t), ctypes.byref(o), _stream(stream)))
+    return problem
+
+
+def tensor_update(problem: TensorProblem, mode: int, stream=None, stats=None, **opts):
+    o = _tensor_options(problem, stats, **opts)
+    t = problem.struct()
+    _native.check(_native.lib().sdl_tensor_update(ctypes.byref(t), mode, ctypes.byref(o), _stream(stream)))
+    return problem
+
+
+def tensor_learn(problem: TensorProblem, K: int, stream=None, stats=None, **opts) -> np.ndarray:
+    """Algorithm 1 with one sweep per mode; returns the RMSE trace (K + 1 values)."""
+    o = _tensor_options(problem, stats, **opts)
+    t = problem.struct()
+    trace = np.zeros(K + 1)
+    _native.check(_native.lib().sdl_tensor_learn(ctypes.byref(t), K, trace.ctypes.data_as(ctypes.c_void_p),
+                                                 ctypes.byref(o), _stream(stream)))
+    return trace
 
 
 def mixed_supported(m1, m2, n1, n2, s) -> bool:

@@ -86,6 +86,7 @@ int get_ctx(hipStream_t st, Ctx** out) {
     if (e == hipSuccess) e = omp_fast_init_device();
     if (e == hipSuccess) e = tmod_sums_bf16_init_device();
     if (e == hipSuccess) e = ortho_init_device();
+    if (e == hipSuccess) e = tensor_init_device();
     if (e != hipSuccess) {
       delete c;
       return fail(SDL_E_DEVICE, "kernel attribute setup: %s", hipGetErrorString(e));
@@ -1003,6 +1004,200 @@ int time_median(hipStream_t st, int reps, double* out, F f) {
   return SDL_OK;
 }
 
+// ------------------------------------------------------------------ n-dimensional signals (Remark 3)
+
+struct TPlan {
+  Plan pl;  // status, counters, iteration counter, RMSE trace
+  void* Dc[kTensorMaxModes];
+  double* G64[kTensorMaxModes];
+  void* Gc[kTensorMaxModes];
+  double *part, *stage, *sums, *w, *rpart;
+  int rows, rblk, nent;
+  size_t bytes;
+};
+
+void tensor_ws_layout(const sdl_tensor_problem* p, size_t elem, int K, void* base, TPlan* tp) {
+  Bump b(base);
+  tp->pl.status = b.take<int>(4);
+  tp->pl.counters = b.take<unsigned long long>(kNumCounters);
+  tp->pl.iter = b.take<int>(1);
+  tp->pl.trace = b.take<double>((size_t)K + 1);
+  int nmax = 1, nent = 1;
+  for (int d = 0; d < p->nmodes; ++d) {
+    tp->Dc[d] = b.take<char>(elem * p->m[d] * p->n[d]);
+    tp->G64[d] = b.take<double>((size_t)p->n[d] * p->n[d]);
+    tp->Gc[d] = b.take<char>(elem * p->n[d] * p->n[d]);
+    nmax = p->n[d] > nmax ? p->n[d] : nmax;
+    const int e = p->n[d] * p->n[d] + p->m[d] * p->n[d];
+    nent = e > nent ? e : nent;
+  }
+  tp->rows = tensor_sums_rows(p->N);
+  tp->nent = nent;
+  tp->part = b.take<double>((size_t)tp->rows * nent);
+  tp->stage = b.take<double>((size_t)reduce_stage_rows(tp->rows) * nent);
+  tp->sums = b.take<double>((size_t)nent);
+  tp->w = b.take<double>((size_t)nmax);
+  tp->rblk = rmse_num_blocks(p->N);
+  tp->rpart = b.take<double>((size_t)tp->rblk);
+  tp->bytes = b.off + 256;
+  tp->pl.bytes = tp->bytes;
+}
+
+int64_t tensor_elems(const int32_t* v, int nm) {
+  int64_t e = 1;
+  for (int d = 0; d < nm; ++d) e *= v[d];
+  return e;
+}
+
+int validate_tensor(const sdl_tensor_problem* p, const Opt& o, bool update) {
+  SDL_TRY(validate(nullptr, 0, o, false));  // the options alone
+  if (!p) return fail(SDL_E_INVAL, "problem is NULL");
+  if (o.prec != SDL_FP64 && o.prec != SDL_FP32)
+    return fail(SDL_E_UNSUPPORTED, "n-dimensional signals run in SDL_FP64 or SDL_FP32");
+  if (o.kernel != 0 || o.method != 0 || o.schedule != 0 || o.proposer)
+    return fail(SDL_E_UNSUPPORTED, "n-dimensional signals have one kernel, Algorithm 1's schedule and no proposer");
+  if (o.workspace) return fail(SDL_E_UNSUPPORTED, "n-dimensional calls use the library's own workspace");
+  if (p->nmodes < 2 || p->nmodes > SDL_TENSOR_MAX_MODES)
+    return fail(SDL_E_SHAPE, "nmodes = %d (2..%d)", p->nmodes, SDL_TENSOR_MAX_MODES);
+  const int nm = p->nmodes;
+  for (int d = 0; d < nm; ++d) {
+    if (p->m[d] <= 0 || p->n[d] <= 0 || p->m[d] > SDL_MAX_M || p->n[d] > SDL_MAX_N)
+      return fail(SDL_E_SHAPE, "mode %d: m = %d, n = %d (1..%d, 1..%d)", d + 1, p->m[d], p->n[d], SDL_MAX_M,
+                  SDL_MAX_N);
+    if (!p->D[d]) return fail(SDL_E_INVAL, "mode %d: dictionary is NULL", d + 1);
+  }
+  const int64_t M = tensor_elems(p->m, nm), A = tensor_elems(p->n, nm);
+  if (M > SDL_TENSOR_MAX_ELEMS || A > SDL_TENSOR_MAX_ELEMS)
+    return fail(SDL_E_SHAPE, "prod m = %lld, prod n = %lld (at most %d each)", (long long)M, (long long)A,
+                SDL_TENSOR_MAX_ELEMS);
+  if (p->s <= 0 || p->s > SDL_MAX_S || p->s > M || p->s > A)
+    return fail(SDL_E_SHAPE, "s = %d (1..%d, at most prod m and prod n)", p->s, SDL_MAX_S);
+  if (p->N < 0) return fail(SDL_E_INVAL, "N = %lld < 0", (long long)p->N);
+  if (p->N > 0 && (!p->Y || !p->supp || !p->coef)) return fail(SDL_E_INVAL, "Y/supp/coef is NULL");
+  const size_t elem = o.prec == SDL_FP64 ? 8 : 4;
+  int m[kTensorMaxModes], n[kTensorMaxModes];
+  for (int d = 0; d < kTensorMaxModes; ++d) {
+    m[d] = d < nm ? p->m[d] : 1;
+    n[d] = d < nm ? p->n[d] : 1;
+  }
+  if (tensor_omp_lds_bytes(nm, m, n, p->s, elem) > 160 * 1024)
+    return fail(SDL_E_UNSUPPORTED, "the working set of one signal exceeds the 160 KiB LDS");
+  if (update)
+    for (int d = 0; d < nm; ++d)
+      if (tensor_sums_lds(nm, m, n, d, elem) > 160 * 1024)
+        return fail(SDL_E_UNSUPPORTED, "mode %d: the update's working set exceeds the 160 KiB LDS", d + 1);
+  return SDL_OK;
+}
+
+template <typename T>
+TensorArgs<T> tensor_args(const sdl_tensor_problem* p, const TPlan& tp, const Opt& o) {
+  TensorArgs<T> a;
+  a.nmodes = p->nmodes;
+  a.s = p->s;
+  for (int d = 0; d < kTensorMaxModes; ++d) {
+    const bool on = d < p->nmodes;
+    a.m[d] = on ? p->m[d] : 1;
+    a.n[d] = on ? p->n[d] : 1;
+    a.D[d] = on ? (const T*)tp.Dc[d] : nullptr;
+    a.G[d] = on ? (const T*)tp.Gc[d] : nullptr;
+  }
+  a.N = p->N;
+  a.Y = (const T*)p->Y;
+  a.supp = p->supp;
+  a.coef = (T*)p->coef;
+  a.res2 = (T*)p->res2;
+  a.stop_rel = o.stop_rel;
+  a.dep_eps = o.dep_eps;
+  a.pivot_fp64 = o.pivot_fp64;
+  a.err2 = o.err2;
+  a.counters = tp.pl.counters;
+  return a;
+}
+
+template <typename T>
+int tensor_prep(const sdl_tensor_problem* p, const TPlan& tp, hipStream_t st) {
+  for (int d = 0; d < p->nmodes; ++d)
+    HIP_TRY(launch_dict_prep<T>(p->D[d], p->m[d], p->n[d], (T*)tp.Dc[d], tp.G64[d], (T*)tp.Gc[d], st));
+  return SDL_OK;
+}
+
+// mode d (0-based) update from the codes: sums, fixed-order reduction, FP64 solve with
+// normalisation, then (rescale) the codes' rescaling by the column norms
+template <typename T>
+int tensor_update_mode(const sdl_tensor_problem* p, const TPlan& tp, const Opt& o, int d, bool rescale,
+                       hipStream_t st) {
+  const TensorArgs<T> a = tensor_args<T>(p, tp, o);
+  const int na = p->n[d], mr = p->m[d], nent = na * na + mr * na;
+  HIP_TRY(launch_tensor_sums<T>(a, d, tp.part, st));
+  const double* src = nullptr;
+  hipError_t e;
+  const int nrow = launch_reduce_stage1(tp.part, tp.rows, nent, tp.stage, &src, st, &e);
+  HIP_TRY(e);
+  const RmseOut none{nullptr, nullptr, 0, 0, 0.0};
+  HIP_TRY(launch_tmod_solve<T>(src, nrow, nent, tp.sums, mr, na, p->D[d], (T*)tp.Dc[d], tp.G64[d], (T*)tp.Gc[d],
+                               tp.w, tp.pl.status, tp.pl.counters, none, st));
+  if (rescale) HIP_TRY(launch_tensor_rescale<T>(a, d, tp.w, st));
+  return SDL_OK;
+}
+
+template <typename T>
+int tensor_check_finite(const sdl_tensor_problem* p, const TPlan& tp, hipStream_t st) {
+  HIP_TRY(launch_check_finite<T>((const T*)p->Y, p->N * tensor_elems(p->m, p->nmodes), tp.pl.status, st));
+  for (int d = 0; d < p->nmodes; ++d)
+    HIP_TRY(launch_check_finite<double>(p->D[d], (int64_t)p->m[d] * p->n[d], tp.pl.status, st));
+  return SDL_OK;
+}
+
+// call: 0 sparse coding, 1 one mode's update (mode 0-based), 2 learning (K iterations)
+template <typename T>
+int tensor_impl(const sdl_tensor_problem* p, int call, int mode, int K, double* trace, const Opt& o, hipStream_t st) {
+  Ctx* ctx;
+  SDL_TRY(get_ctx(st, &ctx));
+  TPlan tp;
+  tensor_ws_layout(p, sizeof(T), K, nullptr, &tp);
+  SDL_TRY_WS(ensure_ws(ctx, tp.bytes, st));
+  tensor_ws_layout(p, sizeof(T), K, ctx->ws, &tp);
+  std::vector<std::pair<int, int>> marks;
+  SDL_TRY(begin_call(st, ctx, tp.pl, 1));
+  if (o.check_finite) {
+    SDL_TRY(tensor_check_finite<T>(p, tp, st));
+    SDL_TRY(finish_call(st, ctx, tp.pl, o, marks, true));
+  }
+  SDL_TRY(tensor_prep<T>(p, tp, st));
+  const TensorArgs<T> a = tensor_args<T>(p, tp, o);
+  const double denom = (double)p->N * (double)tensor_elems(p->m, p->nmodes);
+  if (call == 0) {
+    HIP_TRY(launch_tensor_omp<T>(a, st));
+    return finish_call(st, ctx, tp.pl, o, marks, false);
+  }
+  if (call == 1) {
+    if (p->N > 0) SDL_TRY(tensor_update_mode<T>(p, tp, o, mode, true, st));
+    return finish_call(st, ctx, tp.pl, o, marks, true);
+  }
+  // Algorithm 1 with one sweep per mode: codes, then that mode's dictionary
+  for (int it = 0; it < K && p->N > 0; ++it)
+    for (int d = 0; d < p->nmodes; ++d) {
+      HIP_TRY(launch_tensor_omp<T>(a, st));
+      if (d == 0 && p->res2)
+        HIP_TRY(launch_rmse<T>((const T*)p->res2, p->N, denom, tp.rpart, tp.rblk, tp.pl.trace, 1, 0, tp.pl.iter, st));
+      SDL_TRY(tensor_update_mode<T>(p, tp, o, d, false, st));
+    }
+  if (p->N > 0) {
+    HIP_TRY(launch_tensor_omp<T>(a, st));
+    if (p->res2)
+      HIP_TRY(launch_rmse<T>((const T*)p->res2, p->N, denom, tp.rpart, tp.rblk, tp.pl.trace, 1, 0, tp.pl.iter, st));
+  }
+  int rc = finish_call(st, ctx, tp.pl, o, marks, true);
+  if (trace && (rc == SDL_OK || rc == SDL_E_SINGULAR)) {
+    if (p->N > 0 && p->res2) {
+      HIP_TRY(hipMemcpy(trace, tp.pl.trace, sizeof(double) * ((size_t)K + 1), hipMemcpyDeviceToHost));
+    } else {
+      for (int i = 0; i <= K; ++i) trace[i] = 0.0;
+    }
+  }
+  return rc;
+}
+
 template <typename T>
 int patches_to_image_impl(const sdl_problem* p, int H, int W, const Opt& o, void* image, hipStream_t st) {
   Ctx* ctx;
@@ -1106,6 +1301,37 @@ int sdl_patches_to_image(const sdl_problem* p, int32_t H, int32_t W, const sdl_o
   hipStream_t st = (hipStream_t)stream;
   return opt.prec == SDL_FP64 ? patches_to_image_impl<double>(&q, H, W, opt, image, st)
                               : patches_to_image_impl<float>(&q, H, W, opt, image, st);
+}
+
+int sdl_tensor_sparse_code(const sdl_tensor_problem* p, const sdl_options* o, void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  SDL_TRY(validate_tensor(p, opt, false));
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? tensor_impl<double>(p, 0, 0, 0, nullptr, opt, st)
+                              : tensor_impl<float>(p, 0, 0, 0, nullptr, opt, st);
+}
+
+int sdl_tensor_update(const sdl_tensor_problem* p, int32_t mode, const sdl_options* o, void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  SDL_TRY(validate_tensor(p, opt, true));
+  if (mode < 1 || mode > p->nmodes) return fail(SDL_E_INVAL, "mode = %d (1..%d)", mode, p->nmodes);
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? tensor_impl<double>(p, 1, mode - 1, 0, nullptr, opt, st)
+                              : tensor_impl<float>(p, 1, mode - 1, 0, nullptr, opt, st);
+}
+
+int sdl_tensor_learn(const sdl_tensor_problem* p, int32_t K, double* rmse_trace, const sdl_options* o,
+                     void* stream) {
+  g_err.clear();
+  Opt opt = resolve(o);
+  SDL_TRY(validate_tensor(p, opt, true));
+  if (K < 0) return fail(SDL_E_INVAL, "K = %d < 0", K);
+  if (p->N > 0 && !p->res2) return fail(SDL_E_INVAL, "sdl_tensor_learn needs res2");
+  hipStream_t st = (hipStream_t)stream;
+  return opt.prec == SDL_FP64 ? tensor_impl<double>(p, 2, 0, K, rmse_trace, opt, st)
+                              : tensor_impl<float>(p, 2, 0, K, rmse_trace, opt, st);
 }
 
 int sdl_mixed_supported(int32_t m1, int32_t m2, int32_t n1, int32_t n2, int32_t s) {

@@ -211,6 +211,34 @@ template <typename T>
 hipError_t launch_check_finite(const T* x, int64_t n, int* status, hipStream_t st);
 hipError_t launch_check_finite_bf16(const uint16_t* x, int64_t n, int* status, hipStream_t st);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
+// n-dimensional signals (Remark 3, tensor.hip): m[d] x n[d] dictionaries per mode, atom
+// a = i_0 + n_0 (i_1 + n_1 (...)); entries of m and n beyond nmodes are 1.
+constexpr int kTensorMaxModes = 4;
+template <typename T>
+struct TensorArgs {
+  int nmodes, s;
+  int m[kTensorMaxModes], n[kTensorMaxModes];
+  int64_t N;
+  const T* Y;
+  const T* D[kTensorMaxModes];  // compute-type copies, column-major
+  const T* G[kTensorMaxModes];  // their Gram matrices
+  int32_t* supp;
+  T* coef;
+  T* res2;  // may be null
+  double stop_rel, dep_eps, pivot_fp64, err2;
+  unsigned long long* counters;
+};
+size_t tensor_omp_lds_bytes(int nmodes, const int* m, const int* n, int s, size_t elem);
+size_t tensor_sums_lds(int nmodes, const int* m, const int* n, int mode, size_t elem);
+int tensor_sums_rows(int64_t N);  // partial rows written by launch_tensor_sums
+template <typename T>
+hipError_t launch_tensor_omp(const TensorArgs<T>& a, hipStream_t st);
+// sums of the update of mode `mode` (0-based): one row of n^2 + m n doubles per partial row
+template <typename T>
+hipError_t launch_tensor_sums(const TensorArgs<T>& a, int mode, double* part, hipStream_t st);
+template <typename T>
+hipError_t launch_tensor_rescale(const TensorArgs<T>& a, int mode, const double* w, hipStream_t st);
+hipError_t tensor_init_device();
 // Denoising driver (denoise.hip): overlapping patches of a row-major image as column-major
 // signals, and the image rebuilt as the average of the coded patches covering each pixel.
 template <typename T>

@@ -271,3 +271,53 @@ def overcomplete_dct(m: int, n: int) -> np.ndarray:
     k = np.arange(n)[None, :]
     d = np.cos(np.pi * i * k / n)
     return d / np.linalg.norm(d, axis=0)
+
+
+@dataclasses.dataclass
+class TensorWorkload:
+    """n-dimensional signals (Remark 3): Y_k = X_k x_1 D_1 ... x_n D_n + sigma E with s planted atoms
+    per signal (uniform over prod n atoms), N(0,1) coefficients and unit-norm random dictionaries."""
+    name: str
+    ms: tuple
+    ns: tuple
+    s: int
+    N: int
+    snr_db: float
+    seed: int
+    iters: int
+
+    def sigma(self) -> float:
+        return math.sqrt(self.s / float(np.prod(self.ms)) * 10.0 ** (-self.snr_db / 10.0))
+
+
+# three-mode stand-in for hyperspectral patches: 8 x 8 pixels x 4 bands
+TENSOR_WORKLOADS = {
+    "tensor_8x8x4_n12x12x6_s8": TensorWorkload("tensor_8x8x4_n12x12x6_s8", (8, 8, 4), (12, 12, 6), 8, 100_000,
+                                               30.0, 1006, 10),
+}
+
+
+def tensor_dictionaries(w: TensorWorkload, initial: bool = False):
+    base = 20 if initial else 12  # streams 12.. (true) and 20.. (starting dictionaries), one per mode
+    return [unit_norm_dictionary(w.seed, base + d, m, n) for d, (m, n) in enumerate(zip(w.ms, w.ns))]
+
+
+def tensor_signals(w: TensorWorkload, k0: int = 0, k1: int | None = None, chunk: int = 20000) -> np.ndarray:
+    """Signals k0..k1-1 in math layout (n, m_1, ..., m_n); counters as for the two-mode workloads
+    (supports stream 2, coefficients stream 3), noise from stream 4 at counter k * prod(m) + pixel."""
+    k1 = w.N if k1 is None else k1
+    Ds = tensor_dictionaries(w)
+    M = int(np.prod(w.ms))
+    K = Ds[0]
+    for D in Ds[1:]:
+        K = np.kron(D, K)
+    out = np.empty((k1 - k0,) + tuple(w.ms))
+    for c0 in range(k0, k1, chunk):
+        c1 = min(k1, c0 + chunk)
+        supp = random_supports(w.seed, c0, c1, int(np.prod(w.ns)), w.s)
+        coef = random_coefficients(w.seed, c0, c1, w.s, "normal")
+        y = np.einsum("mkt,kt->km", K[:, supp], coef, optimize=True)
+        y += w.sigma() * normal(w.seed, 4, np.arange(c0 * M, c1 * M, dtype=np.int64)).reshape(c1 - c0, M)
+        out[c0 - k0:c1 - k0] = y.reshape((c1 - c0,) + tuple(reversed(w.ms))).transpose(
+            (0,) + tuple(range(len(w.ms), 0, -1)))
+    return out

@@ -15,7 +15,10 @@ def tie_gap(Y, d1, d2, prefix, gpu_atom, oracle_atom):
     """At the first diverging step: (|corr| of the best unselected atom - |corr| of the GPU's pick,
     the best |corr|, ||Y||_F).  The residual of the common prefix is taken by numpy lstsq on the
     explicit Kronecker columns, independently of both implementations."""
-    K = kron_cols(d1, d2)
+    return _tie_gap(Y, kron_cols(d1, d2), prefix, gpu_atom, oracle_atom)
+
+
+def _tie_gap(Y, K, prefix, gpu_atom, oracle_atom):
     y = Y.flatten("F")
     if prefix:
         x = np.linalg.lstsq(K[:, prefix], y, rcond=None)[0]
@@ -28,7 +31,15 @@ def tie_gap(Y, d1, d2, prefix, gpu_atom, oracle_atom):
     return top - min(c[gpu_atom], c[oracle_atom]), top, float(np.linalg.norm(y))
 
 
-def code_stats(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band):
+def kron_all(Ds):
+    """D_n (x) ... (x) D_1 for n-dimensional signals (first index fastest)."""
+    K = Ds[0]
+    for D in Ds[1:]:
+        K = np.kron(D, K)
+    return K
+
+
+def code_stats(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band, K=None):
     """Supports and coefficients of the GPU against the oracle's.
 
     A signal whose support differs is a classified near-tie when, at the first step where the two
@@ -43,7 +54,7 @@ def code_stats(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band):
         prefix = [int(a) for a in supp_o[k, :t]]
         ga, oa = int(supp_g[k, t]), int(supp_o[k, t])
         if ga >= 0 and oa >= 0:
-            gap, top, yn = tie_gap(Y[k], d1, d2, prefix, ga, oa)
+            gap, top, yn = _tie_gap(Y[k], K if K is not None else kron_cols(d1, d2), prefix, ga, oa)
             gaps.append((int(k), t, gap / top, gap / yn))
             if gap <= band * top:
                 ties += 1
@@ -66,9 +77,10 @@ def code_stats(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band):
                 norm_err=norm_err)
 
 
-def compare_codes(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band, coef_rtol=None):
-    """Returns (n_agree, n_near_tie, n_bad, max element-wise coefficient error) as code_stats defines them."""
-    st = code_stats(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band)
+def compare_codes(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band, coef_rtol=None, K=None):
+    """Returns (n_agree, n_near_tie, n_bad, max element-wise coefficient error) as code_stats defines them.
+    K: explicit dictionary for n-dimensional signals (then d1, d2 are unused)."""
+    st = code_stats(Y, d1, d2, supp_g, coef_g, supp_o, coef_o, band, K=K)
     if st["bad"]:
         print("unclassified support mismatches (signal, step, gap/best, gap/||Y||):", st["gaps"][:10])
     print("coefficients: element-wise err %.2e (worst at |x|/max %.2e, |dx|/max %.2e), normwise err %.2e"

@@ -20,7 +20,7 @@ def test_header_symbols_exported():
     lib = _native.lib()
     for n in names:
         assert hasattr(lib, n)
-    assert lib.sdl_abi_version() == 8
+    assert lib.sdl_abi_version() == 9
 
 
 def _problem(**kw):
@@ -221,7 +221,7 @@ def test_orthonormal_method_validation():
     o = _native.default_options()
     o.reserved1 = 3
     assert _call("sparse_code", _problem(), o) == -1
-    assert lib.sdl_abi_version() == 8
+    assert lib.sdl_abi_version() == 9
 
 
 
@@ -241,3 +241,44 @@ def test_denoise_driver_validation():
     assert lib.sdl_patches_to_image(arr, 7, 16, ctypes.byref(o), ctypes.c_void_p(7), None) == -2
     o.prec = 2  # SDL_BF16 codes are FP32; the image is FP32 or FP64
     assert lib.sdl_patches_to_image(arr, 16, 16, ctypes.byref(o), ctypes.c_void_p(7), None) == -1
+
+
+def _tensor(**kw):
+    t = _native.TensorProblem()
+    t.nmodes, t.s, t.N = kw.get("nmodes", 3), kw.get("s", 4), kw.get("N", 10)
+    ms, ns = kw.get("m", (4, 3, 5)), kw.get("n", (6, 5, 7))
+    for d in range(len(ms)):
+        t.m[d], t.n[d] = ms[d], ns[d]
+        t.D[d] = 8 + d
+    t.Y, t.supp, t.coef, t.res2 = kw.get("Y", 1), 2, 3, 4
+    return t
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nmodes=1), -2), (dict(nmodes=5), -2), (dict(m=(0, 3, 5)), -2), (dict(n=(6, 65, 7)), -2),
+    (dict(m=(64, 64, 2), n=(2, 2, 2)), -2),    # prod m > 4096
+    (dict(s=0), -2), (dict(s=33), -2), (dict(s=30, m=(2, 2, 2)), -2), (dict(N=-1), -1), (dict(Y=None), -1),
+])
+def test_tensor_validation(kw, status):
+    lib = _native.lib()
+    o = _native.default_options()
+    t = _tensor(**kw)
+    assert lib.sdl_tensor_sparse_code(ctypes.byref(t), ctypes.byref(o), None) == status
+    assert lib.sdl_tensor_learn(ctypes.byref(t), 2, None, ctypes.byref(o), None) == status
+
+
+def test_tensor_option_refusals():
+    lib = _native.lib()
+    t = _tensor()
+    for field, value in [("prec", 2), ("prec", 3), ("kernel", 2), ("method", 1), ("schedule", 1)]:
+        o = _native.default_options()
+        setattr(o, field, value)
+        assert lib.sdl_tensor_sparse_code(ctypes.byref(t), ctypes.byref(o), None) == -7, field
+    o = _native.default_options()
+    assert lib.sdl_tensor_update(ctypes.byref(t), 0, ctypes.byref(o), None) == -1
+    assert lib.sdl_tensor_update(ctypes.byref(t), 4, ctypes.byref(o), None) == -1
+    assert lib.sdl_tensor_learn(ctypes.byref(t), -1, None, ctypes.byref(o), None) == -1
+    t.res2 = None
+    assert lib.sdl_tensor_learn(ctypes.byref(t), 2, None, ctypes.byref(o), None) == -1
+    t.D[1] = None
+    assert lib.sdl_tensor_sparse_code(ctypes.byref(t), ctypes.byref(o), None) == -1
