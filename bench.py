@@ -394,6 +394,52 @@ def denoise_workload(api, oracle, synth):
     return out
 
 
+def tensor_workload(api, synth):
+    """Remark 3's n-dimensional generalisation on a three-mode stand-in for hyperspectral patches:
+    100,000 FP32 signals of 8 x 8 x 4, dictionaries 8 x 12, 8 x 12, 4 x 6 (864 atoms), s = 8,
+    K = 10 iterations of Algorithm 1 with one sweep per mode (three sparse codings and three
+    dictionary updates per iteration); plus one sparse-coding launch timed alone."""
+    import torch
+    from oracle import tensor as ot
+    w = synth.TENSOR_WORKLOADS["tensor_8x8x4_n12x12x6_s8"]
+    Y = synth.tensor_signals(w)
+    E = synth.tensor_dictionaries(w, initial=True)
+    pr = api.TensorProblem.from_math(Y, E, w.s, dtype=torch.float32)
+    D0 = [d.clone() for d in pr.Ds]
+    traces = []
+
+    def run():
+        for d, d0 in zip(pr.Ds, D0):
+            d.copy_(d0)
+        traces.append(api.tensor_learn(pr, w.iters))
+
+    run()
+    dt, _, _ = timed_runs(run, 3)
+    pc = api.TensorProblem.from_math(Y, pr.dicts(), w.s, dtype=torch.float32)
+    api.tensor_sparse_code(pc)
+    _, code_s, _ = timed_runs(lambda: api.tensor_sparse_code(pc), 5)
+    ms_, ns_ = w.ms, w.ns
+    fc, pre, post = 0, 1, int(np.prod(ms_))
+    for d in range(len(ms_)):
+        post //= ms_[d]
+        fc += 2 * pre * ns_[d] * ms_[d] * post
+        pre *= ns_[d]
+    A = int(np.prod(ns_))
+    flops = w.N * (fc + w.s * (w.s + 1) * A)
+    nsub = 500
+    so, _, ro = ot.tensor_omp(Y[:nsub].astype(np.float32).astype(np.float64), pr.dicts(), w.s)
+    rg = pc.res2[:nsub].double().cpu().numpy()
+    return {"workload": w.name, "N": w.N, "modes": list(ms_), "atoms": list(ns_), "s": w.s, "steps": w.iters,
+            "value": w.N * w.iters / dt, "unit": "signals/s per iteration (three sweeps and updates each)",
+            "ms_per_step": dt / w.iters * 1e3, "rmse_first": float(traces[-1][0]),
+            "rmse_final": float(traces[-1][-1]),
+            "rmse_vs_oracle": float(np.sqrt(rg.mean()) / np.sqrt(ro.mean())),
+            **support_agreement(pc.supp[:nsub].cpu().numpy(), so),
+            "code_ms": code_s * 1e3, "code_tflops": flops / code_s / 1e12,
+            "code_frac_fp32": flops / code_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+            "code_kernel": "tensor_omp_kernel<float, 3> (one wave per signal, all in LDS)"}
+
+
 def uneven_workload(api, oracle, synth):
     """The uneven batch: four problems of different shapes and sizes (370k signals in all)
     learned together in one call, K = 10."""
@@ -479,6 +525,7 @@ def main():
     ap.add_argument("--no-error-driven", action="store_true")
     ap.add_argument("--no-ortho", action="store_true")
     ap.add_argument("--no-denoise", action="store_true")
+    ap.add_argument("--no-tensor", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one elementwise FP32 copy of MIB MiB (reads and writes MIB MiB): "
                          "the reference dispatch that scales hardware byte counters")
@@ -576,6 +623,7 @@ def main():
     errdriven = None if args.no_error_driven else error_driven_workload(api, oracle, synth)
     ortho = None if args.no_ortho else ortho_workload(api, oracle, synth)
     denoise = None if args.no_denoise else denoise_workload(api, oracle, synth)
+    tensor = None if args.no_tensor else tensor_workload(api, synth)
 
     symbol = kernel_symbol(w, tuned)
     out = {
@@ -619,6 +667,7 @@ def main():
         "error_driven": errdriven,
         "orthonormal": ortho,
         "denoising": denoise,
+        "tensor": tensor,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
