@@ -438,6 +438,14 @@ int learned_prepare(sdl_proposer* P, int64_t N) {
 // Proposal + least squares for all signals, then the register-resident 2D-OMP on the
 // rejected ones (gathered by index).  Needs the FP32 copies of D and the Grams: they are
 // computed here from the FP64 dictionaries.  Writes accept[] (1 = proposal kept).
+// counters[kCtrProposed] += n, counters[kCtrFallback] += *count (one thread; graph-capturable)
+__global__ void count_fallbacks_kernel(const int32_t* count, int64_t n, unsigned long long* counters) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    counters[kCtrProposed] += (unsigned long long)n;
+    counters[kCtrFallback] += (unsigned long long)*count;
+  }
+}
+
 int learned_code(sdl_proposer* P, const sdl_problem& r, double tau, int32_t* accept_out, const OmpArgs<float>& omp,
                  hipStream_t st, int64_t* nfallback_host) {
   ST(learned_prepare(P, r.N));
@@ -472,6 +480,10 @@ int learned_code(sdl_proposer* P, const sdl_problem& r, double tau, int32_t* acc
   a.index = P->list;
   a.count = P->count;
   HT(launch_omp_fast<float>(a, st));
+  if (omp.counters) {
+    hipLaunchKernelGGL(count_fallbacks_kernel, dim3(1), dim3(64), 0, st, (const int32_t*)P->count, r.N, omp.counters);
+    HT(hipGetLastError());
+  }
   if (nfallback_host) {
     int32_t c = 0;
     HT(hipMemcpyAsync(&c, P->count, sizeof(int32_t), hipMemcpyDeviceToHost, st));

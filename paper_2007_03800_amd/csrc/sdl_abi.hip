@@ -584,6 +584,8 @@ int finish_call(hipStream_t st, Ctx* ctx, const Plan& pl, const Opt& o, std::vec
     o.stats->singular_updates += (int64_t)ctr[kCtrSingular];
     o.stats->near_tie_rescores += (int64_t)ctr[kCtrRescored];
     o.stats->near_tie_overflows += (int64_t)ctr[kCtrTieOverflow];
+    o.stats->proposals_accepted += (int64_t)(ctr[kCtrProposed] - ctr[kCtrFallback]);
+    o.stats->fallbacks += (int64_t)ctr[kCtrFallback];
     for (auto& m : marks) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[m.second], ctx->ev[m.second + 1]));
@@ -1528,19 +1530,11 @@ int sdl_learned_sparse_code(sdl_proposer* P, const sdl_problem* p, int32_t nprob
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, false, ctx, &marks};
   SDL_TRY(begin_call(st, ctx, pl, nprob));
-  int64_t fb_total = 0, n_total = 0;
   for (int q = 0; q < nprob; ++q) {
     if (p[q].N == 0) continue;
     SDL_TRY(run_prep<float>(p[q], pl.pb[q], L));
-    int64_t fb = 0;
-    SDL_TRY(learned_code(P, p[q], opt.tau, accept, omp_args<float>(p[q], pl.pb[q], opt, pl), st,
-                         opt.stats ? &fb : nullptr));
-    fb_total += fb;
-    n_total += p[q].N;
-  }
-  if (opt.stats) {
-    opt.stats->fallbacks += fb_total;
-    opt.stats->proposals_accepted += n_total - fb_total;
+    // accepted and fallback counts accumulate in the call's device counters (read by finish_call)
+    SDL_TRY(learned_code(P, p[q], opt.tau, accept, omp_args<float>(p[q], pl.pb[q], opt, pl), st, nullptr));
   }
   return finish_call(st, ctx, pl, opt, marks, opt.stats != nullptr);
 }

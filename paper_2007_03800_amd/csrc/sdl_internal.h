@@ -22,7 +22,9 @@ enum : int {
   kCtrSingular = 3,
   kCtrRescored = 4,     // SDL_MIXED_BF16: signal steps with more than one candidate re-scored in FP32
   kCtrTieOverflow = 5,  // SDL_MIXED_BF16: signal steps where a lane's second key was within the band
-  kNumCounters = 6
+  kCtrProposed = 6,     // learned path: signals given a proposal
+  kCtrFallback = 7,     // learned path: signals whose proposal failed the test (coded by 2D-OMP)
+  kNumCounters = 8
 };
 
 // Arguments of one sparse-coding launch over one problem.

@@ -194,3 +194,76 @@ def test_proposer_save_load_roundtrip(rng, tmp_path):
     Y, _, _, _ = data(rng, 256)
     Yd = torch.from_numpy(np.ascontiguousarray(Y.transpose(0, 2, 1))).float().cuda()
     assert torch.equal(back.logits(Yd), net.logits(Yd))
+
+
+def _oracle_learned_learn(Y, e1, e2, s, K, supp, tau=None):
+    """Algorithm 1 composed from the oracle's calls where every sparse coding takes the proposal
+    supp (the network sees only Y, so its proposal is the same in every sweep): least squares on
+    it, kept where its residual is <= tau ||Y||^2 (tau None: always), else the oracle's 2D-OMP."""
+    yy = np.sum(Y ** 2, axis=(1, 2))
+
+    def code(d1, d2):
+        c, r = mlp.least_squares_on_support(Y, d1, d2, supp)
+        sp = supp.astype(np.int32).copy()
+        if tau is not None:
+            rej = ~(r <= tau * yy)
+            if rej.any():
+                so, co, ro = oracle.omp(Y[rej], d1, d2, s, p=8)
+                sp[rej], c[rej], r[rej] = so, co, ro
+        return sp, c, r
+
+    trace = []
+    for _ in range(K):
+        sp, c, r = code(e1, e2)
+        trace.append(np.sqrt(r.sum() / (len(Y) * Y.shape[1] * Y.shape[2])))
+        e1 = oracle.tmod_update(1, Y, e1, e2, sp, c)[0]
+        sp, c, r = code(e1, e2)
+        e2 = oracle.tmod_update(2, Y, e1, e2, sp, c)[1]
+    sp, c, r = code(e1, e2)
+    trace.append(np.sqrt(r.sum() / (len(Y) * Y.shape[1] * Y.shape[2])))
+    return e1, e2, np.array(trace), r
+
+
+@pytest.mark.parametrize("share", ["all", "half"])
+def test_learn_with_accepted_proposals_matches_oracle(share, rng):
+    """sdl_learn with the learned proposal where proposals are accepted, against Algorithm 1
+    composed from the oracle's calls with the same proposals (the GPU network's top-s supports:
+    the network's input is Y alone, so one proposal per signal serves every sweep).
+    "all": tau accepts every proposal, so every sweep is least squares on the proposal and the
+    updates are the oracle's from those codes (bars: dictionaries and trace 1e-4, FP32 least
+    squares).  "half": tau is the median residual ratio of the proposals at the starting
+    dictionaries, so about half are accepted and the rest take 2D-OMP; the oracle takes each
+    decision from its own FP64 residuals (a decision can flip only for a residual within rounding
+    of the threshold), bars 1e-3."""
+    d1, d2 = rand_dicts(rng, M1, M2, N1, N2)
+    Y, _ = planted(rng, 4000, d1, d2, S, noise=0.05)
+    Y = Y.astype(np.float32).astype(np.float64)
+    e1, e2 = rand_dicts(rng, M1, M2, N1, N2)
+    net = api.Proposer(M1, M2, N1, N2, hidden=128, seed=5)
+    net.set_params(weights(rng, 128))
+    p0 = api.Problem.from_math(Y, e1, e2, S, dtype=torch.float32)
+    acc = torch.zeros(len(Y), dtype=torch.int32, device="cuda")
+    api.learned_sparse_code(net, p0, tau=1e30, accept=acc)
+    torch.cuda.synchronize()
+    assert bool(torch.all(acc == 1))
+    supp = p0.supp.cpu().numpy()
+    yy = np.sum(Y ** 2, axis=(1, 2))
+    tau = 1e30 if share == "all" else float(np.median(p0.res2.cpu().double().numpy() / yy))
+    K = 2
+    o1, o2, otrace, _ = _oracle_learned_learn(Y, e1, e2, S, K, supp, None if share == "all" else tau)
+    pr = api.Problem.from_math(Y, e1, e2, S, dtype=torch.float32)
+    st = api.new_stats()
+    trace = api.learn(pr, K, proposer=net, tau=tau, stats=st)[0]
+    n = st.proposals_accepted + st.fallbacks
+    accepted = st.proposals_accepted / n
+    err = max(np.abs(pr.d1() - o1).max() / np.abs(o1).max(), np.abs(pr.d2() - o2).max() / np.abs(o2).max())
+    print(share, "tau %.3g accepted share %.3f over %d codings; D err %.2e; trace %s oracle %s"
+          % (tau, accepted, n, err, np.round(trace, 6), np.round(otrace, 6)))
+    assert n == len(Y) * (2 * K + 1)
+    bar = 1e-4 if share == "all" else 1e-3
+    if share == "all":
+        assert st.fallbacks == 0
+    else:
+        assert 0.2 < accepted < 0.8
+    assert err <= bar
+    np.testing.assert_allclose(trace, otrace, rtol=bar)
