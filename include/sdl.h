@@ -127,8 +127,11 @@ typedef struct sdl_options {
                                greedy step, a signal whose residual energy ||Y_k - D1 X_k D2^T||_F^2 is
                                <= err2 takes no further atom; s stays the cap (the paper uses
                                eps = 1.15 sigma sqrt(m1 m2), err2 = eps^2, s = m1 m2 / 2).  0 = off
-                               (default); negative or NaN: SDL_E_INVAL.  Runs on the generic kernel:
-                               kernel 2 or 3, or a learned proposal, with err2 > 0 is SDL_E_UNSUPPORTED */
+                               (default); negative or NaN: SDL_E_INVAL.  Runs on the one-wave-per-signal
+                               kernel where one is compiled for the shape (among them the denoising
+                               shapes 8x8 with 16x16 or 8x8 atoms at s = 32) and otherwise on the generic
+                               kernel; kernel 2, kernel 3 without such a kernel, or a learned proposal,
+                               with err2 > 0 is SDL_E_UNSUPPORTED */
   double tie_band;          /* SDL_MIXED_BF16: atoms whose BF16 |correlation| is at least (1 - tie_band) times
                                the largest are re-scored in FP32 and the pick is the largest FP32 |correlation|
                                among them (ties: smallest atom).  Default 2^-6; must be in [0, 0.5) */
@@ -242,6 +245,10 @@ int sdl_image_to_patches(const void* image, int32_t H, int32_t W, int32_t m1, in
  * coef and N = (H-m1+1)(W-m2+1); Y and res2 unused): every pixel is the plain average, over the patches
  * covering it, of D1 X_k D2^T at that pixel (a reading: the paper does not say how overlapping
  * estimates are combined).  options->prec (SDL_FP32 or SDL_FP64) is the type of coef and image.
+ * Unused support slots (-1) may sit anywhere in a code.  The call also needs N*m1*m2 elements of
+ * scratch for the patches' estimates: with options->workspace that buffer must hold them beyond
+ * what sdl_workspace_bytes reports for sparse coding (call 0) of p, rounded up to 256 bytes
+ * (SDL_E_NOMEM otherwise).
  * Asynchronous on `stream`. */
 int sdl_patches_to_image(const sdl_problem* p, int32_t H, int32_t W, const sdl_options* o, void* image,
                          void* stream);

@@ -24,6 +24,9 @@
 //    element), as in the generic kernel and the FP64 reference; in FP32 a repeated pick
 //    stops the signal, as in the other FP32 kernels.
 //  * FP32 pivots below pivot_fp64 * G_aa are recomputed in FP64.
+//  * The error-driven stop (sdl_options.err2, the denoising runs of Sec. IV) tracks the
+//    residual energy by the OMP recurrence ||r||^2 -= corr_a^2 / delta^2 from ||Y||^2 and
+//    takes no further atom once it is <= err2, as the generic kernel does.
 // No TMOD sums epilogue: with this kernel the dictionary updates use the standalone
 // sums kernel.  FP32 shapes compiled in omp_quad.hip are dispatched there instead.
 #include <limits.h>
@@ -95,7 +98,8 @@ __device__ inline void wave_sync() {
 // and the new row are visible to the whole wave.
 template <typename T, class C, class G1f, class G2f>
 __device__ inline bool append_atom(int t, int lane, int ia, int ja, T bs, G1f g1, G2f g2, T* Li, T* gam, T* supi,
-                                   T* supj, T* xg, T* xw, T& my_x, int& my_i, int& my_j, const OmpArgs<T>& a) {
+                                   T* supj, T* xg, T* xw, T& my_x, int& my_i, int& my_j, const OmpArgs<T>& a,
+                                   T& cst_out) {
   const T gaa = g1(ia, ia) * g2(ja, ja);
   // w = L^{-1} g, lane k < t taking row k
   if (lane < t) xg[lane] = g1(my_i, ia) * g2(ja, my_j);
@@ -143,6 +147,7 @@ __device__ inline bool append_atom(int t, int lane, int ia, int ja, T bs, G1f g1
   }
   if (!(d2 > (T)a.dep_eps * gaa)) return false;
   const T cst = bs / d2;
+  cst_out = cst;
   const T dinv = (T)1 / sqrt(d2);
   T* rowt = Li + trow(t);
   if (lane < t) {
@@ -208,7 +213,10 @@ __global__ void __launch_bounds__(kWave* C::WPB)
       ys[e] = v;
       yy += v * v;
     }
-    const T ynorm = sqrt(wave_sum(yy));
+    const T yy_all = wave_sum(yy);
+    const T ynorm = sqrt(yy_all);
+    // residual energy by the OMP recurrence ||r||^2 -= corr_a^2 / pivot (error-driven stop)
+    T renergy = yy_all;
     wave_sync();
     // C = (D1^T Y) D2: W = D1^T Y staged in LDS, then each lane's block of C
     for (int e = lane; e < C::WS; e += kWave) {
@@ -248,6 +256,11 @@ __global__ void __launch_bounds__(kWave* C::WPB)
     const T stop_thr = (T)a.stop_rel * ynorm;
 #pragma unroll 1
     for (; t < S; ++t) {
+      // error-driven stop (denoising runs, Sec. IV): no further atom once ||r||^2 <= err2
+      if (a.err2 > 0.0 && !(renergy > (T)a.err2)) {
+        early = true;
+        break;
+      }
       // largest |corr| over the unselected atoms; ties to the smaller atom index.  A lane
       // scans its atoms in increasing index order (cj, then ri), so a strict comparison
       // keeps the first of equal values.
@@ -281,10 +294,12 @@ __global__ void __launch_bounds__(kWave* C::WPB)
         break;
       }
       const int ia = ba % N1, ja = ba / N1;
-      if (!append_atom<T, C>(t, lane, ia, ja, bs, g1, g2, Li, gam, supi, supj, xg, xw, my_x, my_i, my_j, a)) {
+      T cst = 0;
+      if (!append_atom<T, C>(t, lane, ia, ja, bs, g1, g2, Li, gam, supi, supj, xg, xw, my_x, my_i, my_j, a, cst)) {
         early = true;
         break;
       }
+      renergy -= cst * bs;
       if (act && sr == ia % LR && sc == ja % C::LC) used |= 1ull << ((ia / LR) * NCJ + ja / C::LC);
       if (t + 1 < S && act) {
         // corr <- corr - cst (G_{:,a} - G_{:,S} v): terms gamma_q G1[:, i_q] G2[j_q, :],
@@ -400,7 +415,8 @@ struct MLay {
 template <class C, class G1f, class G2f>
 __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs, G1f g1, G2f g2, float* LiR,
                                       float* LiT, float* gam, float* supi, float* supj, float* xg, float* xw,
-                                      float& my_x, int& my_i, int& my_j, const OmpArgs<float>& a) {
+                                      float& my_x, int& my_i, int& my_j, const OmpArgs<float>& a,
+                                      float& cst_out) {
   constexpr int S = C::S, SP = C::SP, NC = SP / 4;
   const float gaa = g1(ia, ia) * g2(ja, ja);
   if (lane < t) xg[lane] = g1(my_i, ia) * g2(ja, my_j);
@@ -465,6 +481,7 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
   }
   if (!(d2 > (float)a.dep_eps * gaa)) return false;
   const float cst = bs / d2;
+  cst_out = cst;
   const float dinv = 1.f / sqrtf(d2);
   if (lane < t) {
     LiR[t * SP + lane] = -v * dinv;
@@ -544,7 +561,9 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
       ysT[e / M1 + YQ * (e % M1)] = v;
       yy += v * v;
     }
-    const float ynorm = sqrtf(wave_sum(yy));
+    const float yy_all = wave_sum(yy);
+    const float ynorm = sqrtf(yy_all);
+    float renergy = yy_all;  // ||r||^2 by the OMP recurrence (error-driven stop)
     wave_sync();
     {
       // W = D1^T Y, rows padded with zeros to P1
@@ -611,6 +630,10 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
     const float stop_thr = (float)a.stop_rel * ynorm;
 #pragma unroll 1
     for (; t < S; ++t) {
+      if (a.err2 > 0.0 && !(renergy > (float)a.err2)) {
+        early = true;
+        break;
+      }
       // largest |corr| over the unselected atoms, ties to the smaller atom index; a lane's
       // atoms in (tj, ti, v) order have increasing indices, so a strict comparison keeps
       // the first of equal values.  Elements are read by value.
@@ -644,10 +667,13 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
       }
       // the signed correlation from the lane that holds the atom
       bs = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, bs), 16 * ((ia % 16) / 4) + ja % 16));
-      if (!append_atom_sq<C>(t, lane, ia, ja, bs, g1, g2, LiR, LiT, gam, supi, supj, xg, xw, my_x, my_i, my_j, a)) {
+      float cst = 0.f;
+      if (!append_atom_sq<C>(t, lane, ia, ja, bs, g1, g2, LiR, LiT, gam, supi, supj, xg, xw, my_x, my_i, my_j, a,
+                             cst)) {
         early = true;
         break;
       }
+      renergy -= cst * bs;
       if (t + 1 < S) {
         // corr <- corr - cst (G_{:,a} - G_{:,S} v), four terms gamma_q G1[:, i_q] G2[j_q, :]
         // per MFMA (terms beyond t have gamma = 0 and atom 0)
@@ -712,9 +738,11 @@ struct WaveVariant {
 
 // Shapes with a one-wave-per-signal register kernel:
 // (m1, m2, n1, n2, s, lane grid LR x LC, waves per workgroup, FP32 on the matrix cores)
+// The s = 32 entries are the error-driven denoising shapes (8 x 8 patches, cap m1 m2 / 2).
 #define SDL_WAVE_SHAPES(X)                                                                       \
   X(12, 12, 20, 20, 10, 4, 10, 4, true) X(12, 12, 24, 24, 12, 8, 8, 4, true)                    \
-  X(16, 16, 32, 32, 16, 8, 8, 4, true) X(32, 24, 48, 36, 20, 16, 4, 4, true)
+  X(16, 16, 32, 32, 16, 8, 8, 4, true) X(32, 24, 48, 36, 20, 16, 4, 4, true)                    \
+  X(8, 8, 16, 16, 32, 8, 8, 4, true) X(8, 8, 8, 8, 32, 8, 8, 4, true)
 
 const WaveVariant kWaveVariants[] = {
 #define X(A_, B_, C_, D_, E_, F_, G_, H_, I_)                       \

@@ -214,8 +214,8 @@ int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_
     if (o.err2 > 0.0 || o.proposer || o.schedule != 0)
       return fail(SDL_E_UNSUPPORTED, "the orthonormal variant has no error-driven stop, proposer or other schedule");
   }
-  if (o.err2 > 0.0 && (o.kernel == 2 || o.kernel == 3))
-    return fail(SDL_E_UNSUPPORTED, "the error-driven stop runs on the generic kernel (kernel 0 or 1)");
+  if (o.err2 > 0.0 && o.kernel == 2)
+    return fail(SDL_E_UNSUPPORTED, "the error-driven stop does not run on the multi-signal kernels (kernel 2)");
   const size_t elem = o.prec == SDL_FP64 ? 8 : 4;
   for (int q = 0; q < nprob; ++q) {
     const sdl_problem& r = p[q];
@@ -239,6 +239,11 @@ int validate(const sdl_problem* p, int32_t nprob, const Opt& o, bool need_codes_
     if (o.prec == SDL_MIXED_BF16 && !omp_mixed_supported(r.m1, r.m2, r.n1, r.n2, r.s))
       return fail(SDL_E_UNSUPPORTED, "problem %d: no SDL_MIXED_BF16 kernel for m=%dx%d n=%dx%d s=%d", q, r.m1, r.m2,
                   r.n1, r.n2, r.s);
+    if (o.err2 > 0.0 && o.kernel == 3 &&
+        (!omp_wave_supported(r.m1, r.m2, r.n1, r.n2, r.s) ||
+         (o.prec != SDL_FP64 && omp_quad_supported(r.m1, r.m2, r.n1, r.n2, r.s))))
+      return fail(SDL_E_UNSUPPORTED, "problem %d: no one-wave-per-signal kernel with the error-driven stop for this shape",
+                  q);
     if (o.prec == SDL_MIXED_BF16 && (o.err2 > 0.0 || o.proposer))
       return fail(SDL_E_UNSUPPORTED, "SDL_MIXED_BF16 runs plain 2D-OMP (no error-driven stop, no proposer)");
     if (omp_generic_lds_bytes(r.m1, r.m2, r.n1, r.n2, r.s, elem) > 160 * 1024)
@@ -429,8 +434,11 @@ int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, i
   if (o.kernel == 2 && !fast)
     return fail(SDL_E_UNSUPPORTED, "no register-resident kernel for m=%dx%d n=%dx%d s=%d in this precision", r.m1,
                 r.m2, r.n1, r.n2, r.s);
-  const bool wave = !fast && sums_side == 0 && (o.kernel == 0 || o.kernel == 3) && !(o.err2 > 0.0) &&
-                    omp_wave_supported(r.m1, r.m2, r.n1, r.n2, r.s);
+  // the error-driven stop runs on the one-wave-per-signal kernels (not on the quadrant kernel
+  // that serves some FP32 shapes) and on the generic kernel
+  bool wave = !fast && sums_side == 0 && (o.kernel == 0 || o.kernel == 3) &&
+              omp_wave_supported(r.m1, r.m2, r.n1, r.n2, r.s);
+  if (o.err2 > 0.0 && sizeof(T) == 4 && omp_quad_supported(r.m1, r.m2, r.n1, r.n2, r.s)) wave = false;
   if (o.kernel == 3 && !wave)
     return fail(SDL_E_UNSUPPORTED, "no one-wave-per-signal kernel for m=%dx%d n=%dx%d s=%d", r.m1, r.m2, r.n1, r.n2,
                 r.s);
@@ -1206,14 +1214,17 @@ int patches_to_image_impl(const sdl_problem* p, int H, int W, const Opt& o, void
   SDL_TRY(get_ctx(st, &ctx));
   Plan pl;
   layout(p, 1, sizeof(T), 0, nullptr, &pl);
+  // the patches' estimates follow the call's usual workspace
+  const size_t est_off = (pl.bytes + 255) / 256 * 256;
+  const size_t bytes = est_off + sizeof(T) * (size_t)p->N * p->m1 * p->m2;
   void* wsb = nullptr;
-  SDL_TRY(acquire_ws(ctx, o, pl.bytes, st, &wsb));
+  SDL_TRY(acquire_ws(ctx, o, bytes, st, &wsb));
   layout(p, 1, sizeof(T), 0, wsb, &pl);
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, false, ctx, &marks};
   SDL_TRY(run_prep<T>(p[0], pl.pb[0], L));
   HIP_TRY(launch_patches_to_image<T>(p->supp, (const T*)p->coef, (const T*)pl.pb[0].Dc1, (const T*)pl.pb[0].Dc2, H, W,
-                                     p->m1, p->m2, p->n1, p->s, (T*)image, st));
+                                     p->m1, p->m2, p->n1, p->n2, p->s, (T*)((char*)wsb + est_off), (T*)image, st));
   return SDL_OK;
 }
 
@@ -1265,8 +1276,6 @@ int sdl_sparse_code_sums(const sdl_problem* p, int32_t side, double* sums, const
   if (side != 1 && side != 2) return fail(SDL_E_INVAL, "side = %d (1 or 2)", side);
   if (!sums) return fail(SDL_E_INVAL, "sums is NULL");
   if (p->N > 0 && !p->res2) return fail(SDL_E_INVAL, "sdl_sparse_code_sums needs res2");
-  if (opt.err2 > 0.0 && (opt.kernel == 2 || opt.kernel == 3))
-    return fail(SDL_E_UNSUPPORTED, "the error-driven stop runs on the generic kernel (kernel 0 or 1)");
   SDL_TRY(check_workspace(p, 1, 0, opt));
   hipStream_t st = (hipStream_t)stream;
   return opt.prec == SDL_FP64 ? sparse_code_sums_impl<double>(p, side, sums, opt, st)
@@ -1299,7 +1308,6 @@ int sdl_patches_to_image(const sdl_problem* p, int32_t H, int32_t W, const sdl_o
   SDL_TRY(validate(&q, 1, opt, false));
   if (H < p->m1 || W < p->m2 || (int64_t)(H - p->m1 + 1) * (W - p->m2 + 1) != p->N)
     return fail(SDL_E_SHAPE, "N = %lld is not (H - m1 + 1)(W - m2 + 1) for H = %d, W = %d", (long long)p->N, H, W);
-  SDL_TRY(check_workspace(&q, 1, 0, opt));
   hipStream_t st = (hipStream_t)stream;
   return opt.prec == SDL_FP64 ? patches_to_image_impl<double>(&q, H, W, opt, image, st)
                               : patches_to_image_impl<float>(&q, H, W, opt, image, st);

@@ -245,8 +245,9 @@ hipError_t tensor_init_device();
 // signals, and the image rebuilt as the average of the coded patches covering each pixel.
 template <typename T>
 hipError_t launch_image_to_patches(const T* img, int H, int W, int m1, int m2, T* out, hipStream_t st);
+// blocks: (H - m1 + 1)(W - m2 + 1) m1 m2 elements of scratch (the patches' estimates)
 template <typename T>
 hipError_t launch_patches_to_image(const int32_t* supp, const T* coef, const T* D1, const T* D2, int H, int W, int m1,
-                                   int m2, int n1, int s, T* img, hipStream_t st);
+                                   int m2, int n1, int n2, int s, T* blocks, T* img, hipStream_t st);
 
 }  // namespace sdl

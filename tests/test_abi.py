@@ -154,7 +154,8 @@ def test_proposer_file_errors(tmp_path):
 
 
 def test_error_driven_option_validation():
-    """err2 < 0 or NaN is invalid; err2 > 0 needs the generic kernel (checked before device work)."""
+    """err2 < 0 or NaN is invalid; err2 > 0 runs on the one-wave or generic kernels only (kernel 2 is
+    refused, and kernel 3 where the shape has no one-wave kernel; checked before device work)."""
     for bad in (-1.0, float("nan")):
         o = _native.default_options()
         o.err2 = bad
