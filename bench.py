@@ -51,6 +51,11 @@ def sums_flops_executed_per_signal(m1, m2, n1, n2, s):
     return (side1 + side2) / 2
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def median(v):
     v = sorted(v)
     return v[len(v) // 2]
@@ -126,6 +131,7 @@ def learned_vs_plain(args, api, oracle, synth):
     api.sparse_code(tr)
     torch.cuda.synchronize()
     net = api.Proposer(w.m1, w.m2, w.n1, w.n2, hidden=512, seed=7)
+    log("learned leg: training on %d signals" % ntr)
     t0 = time.perf_counter()
     losses = net.train(Ytr, tr.supp, w.s, epochs=8, batch=256, lr=1e-3)
     torch.cuda.synchronize()
@@ -134,6 +140,7 @@ def learned_vs_plain(args, api, oracle, synth):
     del Ytr, tr
     cal = api.Problem(Yev[:20000].contiguous(), D1.clone(), D2.clone(), w.s)
     tau = net.calibrate(cal)
+    log("learned leg: calibrated, timing plain and learned Algorithm 1")
     st = api.new_stats()
     api.learned_sparse_code(net, api.Problem(Yev, D1.clone(), D2.clone(), w.s), tau=tau, stats=st)
     fallback_rate = st.fallbacks / nev
@@ -561,6 +568,7 @@ def main():
     def fresh():
         return api.Problem(Y, torch.from_numpy(d1.T.copy()).to(dev), torch.from_numpy(d2.T.copy()).to(dev), w.s)
 
+    log("plain workload %s: autotune, warm-up, timed runs" % w.name)
     pr = fresh()
     # pick the sparse-coding kernel variant for this shape on this device (outside the timed region)
     if dtype == torch.float32:
@@ -606,25 +614,35 @@ def main():
     rmse_ratio = float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean()))
     agree = support_agreement(pr.supp[:nsub].cpu().numpy(), s_o)
 
+    log("plain workload timed; kernel timing, oracle check")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, oracle, synth, w, d1, d2)
 
     # measured ceilings of this device (copy kernel, FMA and MFMA chains)
+    log("measured ceilings")
     measured = {"hbm_copy_gbs": api.probe_hbm_copy(1 << 30, reps=5)}
     for k in api.PROBE_KINDS:
         measured[k + "_tflops"] = api.probe_peak(k, reps=5)
     peak_meas = measured["fp32_mfma_4x4x1_tflops" if tuned and tuned[3] else "fp32_fma_tflops"]
 
+    log("learned proposal leg")
     learned = None
     if not args.no_learned and dtype == torch.float32:
         learned = learned_vs_plain(args, api, oracle, synth)
+    log("mixed-precision leg")
     mixed = None if args.no_mixed else mixed_workload(api, oracle, synth)
+    log("uneven-batch leg")
     uneven = None if args.no_uneven else uneven_workload(api, oracle, synth)
+    log("error-driven leg")
     errdriven = None if args.no_error_driven else error_driven_workload(api, oracle, synth)
+    log("orthonormal leg")
     ortho = None if args.no_ortho else ortho_workload(api, oracle, synth)
+    log("denoising leg")
     denoise = None if args.no_denoise else denoise_workload(api, oracle, synth)
+    log("n-dimensional leg")
     tensor = None if args.no_tensor else tensor_workload(api, synth)
+    log("done")
 
     symbol = kernel_symbol(w, tuned)
     out = {

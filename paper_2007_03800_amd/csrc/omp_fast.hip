@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
 #pragma unroll
   for (int q = 0; q < C::NTILE; ++q) acc[q * kWave] = f32x4{0.f, 0.f, 0.f, 0.f};
   double racc = 0.0;
+  unsigned n_early = 0;  // early-stopped signals seen by this lane, counted once at the end
   for (int64_t grp = (int64_t)blockIdx.x * kFastWaves + wv; grp < ngroups; grp += (int64_t)gridDim.x * kFastWaves) {
     const int64_t k0 = grp * SPW;
     const int nvalid = (int)((nsig - k0) < SPW ? (nsig - k0) : SPW);
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
       }
       if (sub == 0) {
         if (a.res2) a.res2[k] = rr;
-        if (nsel < S) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+        n_early += nsel < S ? 1u : 0u;
         racc += (double)rr;
       }
     }
@@ -420,6 +421,7 @@ __global__ void __launch_bounds__(kWave* kFastWaves) __attribute__((amdgpu_waves
     }
     wave_sync();  // the staging buffer is rewritten by the next group
   }
+  if (n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
   if (eside) {
     // one partial row per workgroup: [A (na x na) | B (mr x na)] column-major, then sum of
     // res2; the four waves' values are added in wave order

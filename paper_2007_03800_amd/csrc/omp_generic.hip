@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(kWave) omp_generic_kernel(OmpArgs<T> a) {
   T* vs = sm + L.v;
   T* wv = sm + L.wv;
 
+  unsigned n_early = 0;  // early-stopped signals of this wave (lane 0), counted once at the end
   for (int64_t k = blockIdx.x; k < a.N; k += gridDim.x) {
     __syncthreads();
     T yy = 0;
@@ -229,9 +230,10 @@ __global__ void __launch_bounds__(kWave) omp_generic_kernel(OmpArgs<T> a) {
     }
     if (lane == 0) {
       if (a.res2) a.res2[k] = rr;
-      if (early) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+      n_early += early ? 1u : 0u;
     }
   }
+  if (lane == 0 && n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
 }
 
 }  // namespace

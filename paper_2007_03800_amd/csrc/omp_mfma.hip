@@ -218,6 +218,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
   for (int q = 0; q < C::NTILE; ++q) acc[q * kWave] = f32x4{0.f, 0.f, 0.f, 0.f};
   double racc = 0.0;
 
+  unsigned n_early = 0;  // early-stopped signals seen by this lane, counted once at the end
   for (int64_t grp = (int64_t)blockIdx.x * kWaves + wv; grp < ngroups; grp += (int64_t)gridDim.x * kWaves) {
     const int64_t k0 = grp * kSigs;
     const int nvalid = (int)((nsig - k0) < kSigs ? (nsig - k0) : kSigs);
@@ -470,7 +471,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
       }
       if (c == 0) {
         if (a.res2) a.res2[k] = rr;
-        if (nsel < S) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+        n_early += nsel < S ? 1u : 0u;
         racc += (double)rr;
       }
     }
@@ -480,6 +481,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
       sums_epilogue<C, 2>(acc, sWork[wv], ys, sD1, x, ia, ja, g, c, lane);
     wave_sync();
   }
+  if (n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
   if (eside) {
     const int nent = ena * ena + emr * ena;
 #pragma unroll

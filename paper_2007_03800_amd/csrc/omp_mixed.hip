@@ -390,6 +390,7 @@ __global__ void __launch_bounds__(kWave* kXWaves) __attribute__((amdgpu_waves_pe
   w.overflow = 0;
   w.L = sL[wv] + g * C::NLP;
 
+  unsigned n_early = 0;  // early-stopped signals seen by this lane, counted once at the end
   for (int64_t grp = (int64_t)blockIdx.x * kXWaves + wv; grp < ngroups; grp += (int64_t)gridDim.x * kXWaves) {
     const int64_t k0 = grp * kXSigs;
     const int nvalid = (int)((nsig - k0) < kXSigs ? (nsig - k0) : kXSigs);
@@ -452,11 +453,12 @@ __global__ void __launch_bounds__(kWave* kXWaves) __attribute__((amdgpu_waves_pe
       }
       if (c == 0) {
         if (a.res2) a.res2[k] = rr;
-        if (w.nsel < S) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+        n_early += w.nsel < S ? 1u : 0u;
       }
     }
     wave_sync();  // the next group's staging overwrites ys
   }
+  if (n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
   // per-wave totals of the near-tie counters
   unsigned long long n_rescored = w.rescored, n_overflow = w.overflow;
 #pragma unroll

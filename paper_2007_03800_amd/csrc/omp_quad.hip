@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(kWave* kQWaves) __attribute__((amdgpu_waves_pe
   const float* G1q = sG1P + qi * 4 * TI + c * TI;  // + ik NP1: G1[4 (qi TI + bi) + c, ik], bi < TI
   const float* G2q = sG2P + qj * 4 * TJ + c * TJ;  // + jk NP2: G2[jk, 4 (qj TJ + bj) + c], bj < TJ
 
+  unsigned n_early = 0;  // early-stopped signals seen by this lane, counted once at the end
   for (int64_t grp = (int64_t)blockIdx.x * kQWaves + wv; grp < ngroups; grp += (int64_t)gridDim.x * kQWaves) {
     const int64_t k0 = grp * kQSigs;
     const int nvalid = (int)((nsig - k0) < kQSigs ? (nsig - k0) : kQSigs);
@@ -375,11 +376,12 @@ __global__ void __launch_bounds__(kWave* kQWaves) __attribute__((amdgpu_waves_pe
       }
       if (cs == 0) {
         if (a.res2) a.res2[k] = rr;
-        if (nsel < S) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+        n_early += nsel < S ? 1u : 0u;
       }
     }
     wave_sync();  // the next group's staging overwrites ys
   }
+  if (n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
 }
 
 template <class C>

@@ -206,6 +206,7 @@ __global__ void __launch_bounds__(kWave* C::WPB)
   auto g1 = [&](int i, int ik) { return sG1P[ik * N1 + (i % LR) * NRI + i / LR]; };
   auto g2 = [&](int jk, int j) { return sG2P[jk * N2 + (j % C::LC) * NCJ + j / C::LC]; };
 
+  unsigned n_early = 0;  // early-stopped signals of this wave (lane 0), counted once at the end
   for (int64_t k = (int64_t)blockIdx.x * C::WPB + wv; k < a.N; k += (int64_t)gridDim.x * C::WPB) {
     T yy = 0;
     for (int e = lane; e < M; e += kWave) {
@@ -346,10 +347,11 @@ __global__ void __launch_bounds__(kWave* C::WPB)
     }
     if (lane == 0) {
       if (a.res2) a.res2[k] = rr;
-      if (early) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+      n_early += early ? 1u : 0u;
     }
     wave_sync();
   }
+  if (lane == 0 && n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
 }
 
 // Largest (key, atom) pair of the wave, ties to the smaller atom; the result is uniform.
@@ -554,6 +556,7 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
   // register elements outside the n1 x n2 block stay exactly zero (zero rows and columns
   // in every table), so they are never selected
 
+  unsigned n_early = 0;  // early-stopped signals of this wave (lane 0), counted once at the end
   for (int64_t k = (int64_t)blockIdx.x * C::WPB + wv; k < a.N; k += (int64_t)gridDim.x * C::WPB) {
     float yy = 0.f;
     for (int e = lane; e < M; e += kWave) {
@@ -711,10 +714,11 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
     }
     if (lane == 0) {
       if (a.res2) a.res2[k] = rr;
-      if (early) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+      n_early += early ? 1u : 0u;
     }
     wave_sync();
   }
+  if (lane == 0 && n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
 }
 
 // One signal per wave up to kWaveMaxBlocks workgroups (a persistent grid measured slower:

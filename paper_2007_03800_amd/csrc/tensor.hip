@@ -35,9 +35,10 @@ __host__ __device__ inline TLay tensor_layout(int nm, const int* m, const int* n
   for (int d = 0; d < nm; ++d) { l.g[d] = o; o += n[d] * n[d]; }
   int M = 1, A = 1;
   for (int d = 0; d < nm; ++d) { M *= m[d]; A *= n[d]; }
-  // largest intermediate of the mode products: modes < k contracted (n), the rest not (m)
+  // largest intermediate of the mode products: modes < k contracted (n), the rest not (m); the
+  // last product (k = nm) goes straight into the correlations
   int st = M;
-  for (int k = 1; k <= nm; ++k) {
+  for (int k = 1; k < nm; ++k) {
     int e = 1;
     for (int d = 0; d < nm; ++d) e *= d < k ? n[d] : m[d];
     st = e > st ? e : st;
@@ -110,7 +111,17 @@ __global__ void __launch_bounds__(kWave) tensor_omp_kernel(TensorArgs<T> a) {
   int* supp_s = reinterpret_cast<int*>(sm + L.end);
   int* sidx = supp_s + s;  // per-mode indices of the chosen atoms, [t * kTensorMaxModes + d]
   unsigned char* sel = reinterpret_cast<unsigned char*>(sidx + s * kTensorMaxModes);
+  // per-mode indices of every atom, 8 bits each (no integer division in the step loop)
+  int* epk = reinterpret_cast<int*>(sel + ((A + 3) & ~3));
   const int lane = threadIdx.x;
+  for (int e = lane; e < A; e += kWave) {
+    int idx[kTensorMaxModes];
+    split(e, n, nm, idx);
+    int pk = 0;
+#pragma unroll
+    for (int d = 0; d < nm; ++d) pk |= idx[d] << (8 * d);
+    epk[e] = pk;
+  }
   const T* Ds[kTensorMaxModes];
   const T* Gs[kTensorMaxModes];
 #pragma unroll
@@ -131,6 +142,7 @@ __global__ void __launch_bounds__(kWave) tensor_omp_kernel(TensorArgs<T> a) {
   T* vs = sm + L.v;
   T* wv = sm + L.wv;
 
+  unsigned n_early = 0;  // early-stopped signals of this wave (lane 0), counted once at the end
   for (int64_t k = blockIdx.x; k < a.N; k += gridDim.x) {
     __syncthreads();
     T yy = 0;
@@ -246,7 +258,9 @@ __global__ void __launch_bounds__(kWave) tensor_omp_kernel(TensorArgs<T> a) {
         // corr <- corr - cstar (G_{:,a} - G_{:,S} v)
         for (int e = lane; e < A; e += kWave) {
           int ie[kTensorMaxModes];
-          split(e, n, nm, ie);
+          const int pk = epk[e];
+#pragma unroll
+          for (int d = 0; d < nm; ++d) ie[d] = (pk >> (8 * d)) & 0xFF;
           T g = gram(Gs, n, nm, ie, ia);
           for (int q = 0; q < t; ++q) g -= vs[q] * gram(Gs, n, nm, ie, sidx + q * kTensorMaxModes);
           al[e] -= cstar * g;
@@ -277,9 +291,10 @@ __global__ void __launch_bounds__(kWave) tensor_omp_kernel(TensorArgs<T> a) {
     }
     if (lane == 0) {
       if (a.res2) a.res2[k] = rr;
-      if (early) atomicAdd(&a.counters[kCtrEarlyStop], 1ull);
+      n_early += early ? 1u : 0u;
     }
   }
+  if (lane == 0 && n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
 }
 
 // ---------------------------------------------------------------- mode-d sums
@@ -417,7 +432,8 @@ size_t tensor_omp_lds_bytes(int nmodes, const int* m, const int* n, int s, size_
   const TLay l = tensor_layout(nmodes, m, n, s);
   int A = 1;
   for (int d = 0; d < nmodes; ++d) A *= n[d];
-  return (size_t)l.end * elem + sizeof(int) * (size_t)s * (1 + kTensorMaxModes) + (size_t)A + 16;
+  return (size_t)l.end * elem + sizeof(int) * (size_t)s * (1 + kTensorMaxModes) + (size_t)((A + 3) & ~3) +
+         sizeof(int) * (size_t)A + 16;
 }
 
 size_t tensor_sums_lds(int nmodes, const int* m, const int* n, int mode, size_t elem) {
