@@ -756,6 +756,18 @@ const WaveVariant kWaveVariants[] = {
 #undef X
 };
 
+// FP32 one-wave shapes used only by the n-dimensional path, with every mode after the first
+// collapsed into one Kronecker factor D_n (x) ... (x) D_2 (so m2 and n2 are products and may
+// exceed the two-mode limits): (m1, m2, n1, n2, s, LR, LC, waves per workgroup)
+#define SDL_WAVE_COLLAPSED_SHAPES(X) X(8, 32, 12, 72, 8, 4, 8, 4)
+
+const WaveVariant kWaveCollapsed[] = {
+#define X(A_, B_, C_, D_, E_, F_, G_, H_) \
+  {A_, B_, C_, D_, E_, F_, G_, &launch_wcfg<float, WCfg<A_, B_, C_, D_, E_, F_, G_, H_, true>>, nullptr},
+    SDL_WAVE_COLLAPSED_SHAPES(X)
+#undef X
+};
+
 const WaveVariant* find_wave(int m1, int m2, int n1, int n2, int s) {
   for (const WaveVariant& v : kWaveVariants)
     if (v.m1 == m1 && v.m2 == m2 && v.n1 == n1 && v.n2 == n2 && v.s == s) return &v;
@@ -772,6 +784,19 @@ bool omp_wave_grid(int m1, int m2, int n1, int n2, int s, int* lr, int* lc) {
   *lr = v->lr;
   *lc = v->lc;
   return true;
+}
+
+bool omp_wave_collapsed_supported(int m1, int m2, int n1, int n2, int s) {
+  for (const WaveVariant& v : kWaveCollapsed)
+    if (v.m1 == m1 && v.m2 == m2 && v.n1 == n1 && v.n2 == n2 && v.s == s) return true;
+  return false;
+}
+
+hipError_t launch_omp_wave_collapsed(const OmpArgs<float>& a, hipStream_t st) {
+  for (const WaveVariant& v : kWaveCollapsed)
+    if (v.m1 == a.m1 && v.m2 == a.m2 && v.n1 == a.n1 && v.n2 == a.n2 && v.s == a.s)
+      return a.N == 0 ? hipSuccess : v.f32(a, st);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>

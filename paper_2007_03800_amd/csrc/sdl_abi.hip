@@ -1023,8 +1023,26 @@ struct TPlan {
   void* Gc[kTensorMaxModes];
   double *part, *stage, *sums, *w, *rpart;
   int rows, rblk, nent;
+  // FP32 shapes coded by the two-mode one-wave kernel: modes 2.. collapsed into one Kronecker
+  // factor Dk (mk x nk, FP64 master, compute-type copy and Grams)
+  bool collapsed;
+  int mk, nk;
+  double *Dk64, *Gk64;
+  void *Dkc, *Gkc;
   size_t bytes;
 };
+
+bool tensor_collapsed(const sdl_tensor_problem* p, size_t elem) {
+  if (elem != 4) return false;
+  int64_t mk = 1, nk = 1;
+  for (int d = 1; d < p->nmodes; ++d) {
+    mk *= p->m[d];
+    nk *= p->n[d];
+  }
+  // the dictionary preparation stages the factor in LDS at (mk + 1) x nk doubles
+  if ((mk + 1) * nk > (int64_t)(SDL_MAX_M + 1) * SDL_MAX_N) return false;
+  return omp_wave_collapsed_supported(p->m[0], (int)mk, p->n[0], (int)nk, p->s);
+}
 
 void tensor_ws_layout(const sdl_tensor_problem* p, size_t elem, int K, void* base, TPlan* tp) {
   Bump b(base);
@@ -1040,6 +1058,21 @@ void tensor_ws_layout(const sdl_tensor_problem* p, size_t elem, int K, void* bas
     nmax = p->n[d] > nmax ? p->n[d] : nmax;
     const int e = p->n[d] * p->n[d] + p->m[d] * p->n[d];
     nent = e > nent ? e : nent;
+  }
+  tp->collapsed = tensor_collapsed(p, elem);
+  tp->mk = tp->nk = 1;
+  for (int d = 1; d < p->nmodes; ++d) {
+    tp->mk *= p->m[d];
+    tp->nk *= p->n[d];
+  }
+  if (tp->collapsed) {
+    tp->Dk64 = b.take<double>((size_t)tp->mk * tp->nk);
+    tp->Gk64 = b.take<double>((size_t)tp->nk * tp->nk);
+    tp->Dkc = b.take<char>(elem * tp->mk * tp->nk);
+    tp->Gkc = b.take<char>(elem * tp->nk * tp->nk);
+  } else {
+    tp->Dk64 = tp->Gk64 = nullptr;
+    tp->Dkc = tp->Gkc = nullptr;
   }
   tp->rows = tensor_sums_rows(p->N);
   tp->nent = nent;
@@ -1150,6 +1183,48 @@ int tensor_update_mode(const sdl_tensor_problem* p, const TPlan& tp, const Opt& 
   return SDL_OK;
 }
 
+// sparse coding of every signal: the two-mode one-wave kernel on (D_1, D_n (x) ... (x) D_2) for the
+// collapsed FP32 shapes (the same atoms in the same order: a = i_1 + n_1 j', j' = i_2 + n_2 (...)),
+// else the n-mode kernel
+template <typename T>
+int tensor_code(const sdl_tensor_problem* p, const TPlan& tp, const Opt& o, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    if (tp.collapsed) {
+      TensorArgs<double> dd{};
+      dd.nmodes = p->nmodes;
+      for (int d = 0; d < kTensorMaxModes; ++d) {
+        dd.m[d] = d < p->nmodes ? p->m[d] : 1;
+        dd.n[d] = d < p->nmodes ? p->n[d] : 1;
+        dd.D[d] = d < p->nmodes ? p->D[d] : nullptr;
+      }
+      HIP_TRY(launch_kron_tail(dd, tp.Dk64, st));
+      HIP_TRY(launch_dict_prep<float>(tp.Dk64, tp.mk, tp.nk, (float*)tp.Dkc, tp.Gk64, (float*)tp.Gkc, st));
+      OmpArgs<float> a{};
+      a.m1 = p->m[0]; a.m2 = tp.mk; a.n1 = p->n[0]; a.n2 = tp.nk; a.s = p->s; a.N = p->N;
+      a.Y = (const float*)p->Y;
+      a.Yh = nullptr;
+      a.D1 = (const float*)tp.Dc[0];
+      a.D2 = (const float*)tp.Dkc;
+      a.G1 = (const float*)tp.Gc[0];
+      a.G2 = (const float*)tp.Gkc;
+      a.supp = p->supp;
+      a.coef = (float*)p->coef;
+      a.res2 = (float*)p->res2;
+      a.stop_rel = o.stop_rel; a.dep_eps = o.dep_eps; a.pivot_fp64 = o.pivot_fp64; a.err2 = o.err2;
+      a.tie_band = o.tie_band;
+      a.counters = tp.pl.counters;
+      a.sums_side = 0;
+      a.sums_part = nullptr;
+      a.index = nullptr;
+      a.count = nullptr;
+      HIP_TRY(launch_omp_wave_collapsed(a, st));
+      return SDL_OK;
+    }
+  }
+  HIP_TRY(launch_tensor_omp<T>(tensor_args<T>(p, tp, o), st));
+  return SDL_OK;
+}
+
 template <typename T>
 int tensor_check_finite(const sdl_tensor_problem* p, const TPlan& tp, hipStream_t st) {
   HIP_TRY(launch_check_finite<T>((const T*)p->Y, p->N * tensor_elems(p->m, p->nmodes), tp.pl.status, st));
@@ -1174,10 +1249,9 @@ int tensor_impl(const sdl_tensor_problem* p, int call, int mode, int K, double* 
     SDL_TRY(finish_call(st, ctx, tp.pl, o, marks, true));
   }
   SDL_TRY(tensor_prep<T>(p, tp, st));
-  const TensorArgs<T> a = tensor_args<T>(p, tp, o);
   const double denom = (double)p->N * (double)tensor_elems(p->m, p->nmodes);
   if (call == 0) {
-    HIP_TRY(launch_tensor_omp<T>(a, st));
+    SDL_TRY(tensor_code<T>(p, tp, o, st));
     return finish_call(st, ctx, tp.pl, o, marks, false);
   }
   if (call == 1) {
@@ -1187,13 +1261,13 @@ int tensor_impl(const sdl_tensor_problem* p, int call, int mode, int K, double* 
   // Algorithm 1 with one sweep per mode: codes, then that mode's dictionary
   for (int it = 0; it < K && p->N > 0; ++it)
     for (int d = 0; d < p->nmodes; ++d) {
-      HIP_TRY(launch_tensor_omp<T>(a, st));
+      SDL_TRY(tensor_code<T>(p, tp, o, st));
       if (d == 0 && p->res2)
         HIP_TRY(launch_rmse<T>((const T*)p->res2, p->N, denom, tp.rpart, tp.rblk, tp.pl.trace, 1, 0, tp.pl.iter, st));
       SDL_TRY(tensor_update_mode<T>(p, tp, o, d, false, st));
     }
   if (p->N > 0) {
-    HIP_TRY(launch_tensor_omp<T>(a, st));
+    SDL_TRY(tensor_code<T>(p, tp, o, st));
     if (p->res2)
       HIP_TRY(launch_rmse<T>((const T*)p->res2, p->N, denom, tp.rpart, tp.rblk, tp.pl.trace, 1, 0, tp.pl.iter, st));
   }

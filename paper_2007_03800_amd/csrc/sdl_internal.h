@@ -241,6 +241,12 @@ hipError_t launch_tensor_sums(const TensorArgs<T>& a, int mode, double* part, hi
 template <typename T>
 hipError_t launch_tensor_rescale(const TensorArgs<T>& a, int mode, const double* w, hipStream_t st);
 hipError_t tensor_init_device();
+// n-dimensional sparse coding on the two-mode one-wave kernel: the modes after the first
+// collapsed into one Kronecker factor (FP32 shapes compiled in omp_wave.hip)
+bool omp_wave_collapsed_supported(int m1, int m2, int n1, int n2, int s);
+hipError_t launch_omp_wave_collapsed(const OmpArgs<float>& a, hipStream_t st);
+// Dk = D_nm-1 (x) ... (x) D_1 (mode 0 excluded): prod_{d>=1} m[d] x prod_{d>=1} n[d], FP64
+hipError_t launch_kron_tail(const TensorArgs<double>& d, double* Dk, hipStream_t st);
 // Denoising driver (denoise.hip): overlapping patches of a row-major image as column-major
 // signals, and the image rebuilt as the average of the coded patches covering each pixel.
 template <typename T>

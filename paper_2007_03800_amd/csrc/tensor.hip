@@ -417,6 +417,21 @@ __global__ void __launch_bounds__(kWave) tensor_sums_kernel(TensorArgs<T> a, int
   for (int e = lane; e < nent; e += kWave) part[(size_t)blockIdx.x * nent + e] = acc[e];
 }
 
+// Dk[p', j'] = prod_{d>=1} D_d[p_d, i_d] with p' = p_1 + m_1 (p_2 + ...), j' = i_1 + n_1 (i_2 + ...)
+__global__ void kron_tail_kernel(TensorArgs<double> d, double* Dk, int mk, int nk) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < mk * nk; e += gridDim.x * blockDim.x) {
+    int p = e % mk, j = e / mk;
+    double v = 1.0;
+    for (int q = 1; q < d.nmodes; ++q) {
+      const int pq = p % d.m[q], iq = j % d.n[q];
+      p /= d.m[q];
+      j /= d.n[q];
+      v *= d.D[q][pq + d.m[q] * iq];
+    }
+    Dk[e] = v;
+  }
+}
+
 template <typename T>
 __global__ void tensor_rescale_kernel(int64_t n_el, int div, int na, const int32_t* supp, T* coef, const double* w) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -480,6 +495,16 @@ hipError_t launch_tensor_rescale(const TensorArgs<T>& a, int mode, const double*
   for (int d = 0; d < mode; ++d) div *= a.n[d];
   hipLaunchKernelGGL(tensor_rescale_kernel<T>, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, n_el, div,
                      a.n[mode], a.supp, a.coef, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_kron_tail(const TensorArgs<double>& d, double* Dk, hipStream_t st) {
+  int mk = 1, nk = 1;
+  for (int q = 1; q < d.nmodes; ++q) {
+    mk *= d.m[q];
+    nk *= d.n[q];
+  }
+  hipLaunchKernelGGL(kron_tail_kernel, dim3((unsigned)((mk * nk + 255) / 256)), dim3(256), 0, st, d, Dk, mk, nk);
   return hipGetLastError();
 }
 
