@@ -432,6 +432,117 @@ __global__ void kron_tail_kernel(TensorArgs<double> d, double* Dk, int mk, int n
   }
 }
 
+// FP32 mode-d sums on the matrix cores, for n_d <= 16 and m_d <= 16: the signals' W_k(d) and
+// Y_k(d) concatenated along their columns form the contraction A = Wcat Wcat^T, B = Ycat Wcat^T,
+// run four columns at a time with the 16x16x4 FP32 MFMA (lane l supplies row l % 16 of column
+// l / 16 of the slice, which is both operands' value for the A sum).  One wave per workgroup
+// strides over the signals, accumulating in FP32; its tiles are written as one FP64 partial row.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kSumsLdw = 17;  // W column stride (odd: the lanes' columns fall in different banks)
+
+__host__ __device__ inline size_t sums_mfma_lds_bytes(int nm, const int* m, const int* n, int mode) {
+  int M = 1, dsz = 0;
+  for (int d = 0; d < nm; ++d) {
+    M *= m[d];
+    dsz += m[d] * n[d];
+  }
+  const int mo = M / m[mode], mo4 = (mo + 3) / 4 * 4;
+  return sizeof(float) * ((size_t)dsz + M + (size_t)kSumsLdw * mo4) + 2 * sizeof(int) * (size_t)mo4 + 32;
+}
+
+template <int NM>
+__global__ void __launch_bounds__(kWave) tensor_sums_mfma_kernel(TensorArgs<float> a, int mode, double* part) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* sm = reinterpret_cast<float*>(smem_raw);
+  constexpr int nm = NM;
+  const int s = a.s, lane = threadIdx.x;
+  int m[kTensorMaxModes], n[kTensorMaxModes], stride[kTensorMaxModes];
+  int M = 1, dsz = 0;
+  for (int d = 0; d < kTensorMaxModes; ++d) {
+    m[d] = d < nm ? a.m[d] : 1;
+    n[d] = d < nm ? a.n[d] : 1;
+    stride[d] = M;
+    M *= m[d];
+  }
+  const float* Ds[kTensorMaxModes];
+  int off = 0;
+#pragma unroll
+  for (int d = 0; d < nm; ++d) {
+    for (int e = lane; e < m[d] * n[d]; e += kWave) sm[off + e] = a.D[d][e];
+    Ds[d] = sm + off;
+    off += m[d] * n[d];
+    dsz = off;
+  }
+  const int na = n[mode], mr = m[mode], mo = M / mr, mo4 = (mo + 3) / 4 * 4;
+  float* ys = sm + dsz;
+  float* W = ys + M;  // W[i + kSumsLdw c], i < 16, c < mo4 (rows >= na and columns >= mo stay 0)
+  int* cidx = reinterpret_cast<int*>(W + kSumsLdw * mo4);
+  int* cbase = cidx + mo4;
+  for (int c = lane; c < mo4; c += kWave) {
+    int r = c, packed = 0, base = 0;
+#pragma unroll
+    for (int d = 0; d < nm; ++d) {
+      if (d == mode) continue;
+      const int v = r % m[d];
+      r /= m[d];
+      packed |= v << (8 * d);
+      base += v * stride[d];
+    }
+    cidx[c] = packed;
+    cbase[c] = c < mo ? base : -1;
+  }
+  const int r16 = lane % 16, kq = lane / 16;
+  f32x4_t accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t k = blockIdx.x; k < a.N; k += gridDim.x) {
+    __syncthreads();
+    for (int e = lane; e < M; e += kWave) ys[e] = a.Y[k * M + e];
+    for (int c = lane; c < mo4; c += kWave) {
+      float col[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) col[i] = 0.f;
+      if (c < mo) {
+        const int packed = cidx[c];
+        for (int t = 0; t < s; ++t) {
+          const int at = a.supp[k * s + t];
+          if (at < 0) continue;
+          int r = at, id = 0;
+          float v = a.coef[k * s + t];
+#pragma unroll
+          for (int d = 0; d < nm; ++d) {
+            const int i = r % n[d];
+            r /= n[d];
+            if (d == mode) id = i;
+            else v *= Ds[d][((packed >> (8 * d)) & 0xFF) + m[d] * i];
+          }
+          // selection order within the column: the same sums as adding element by element
+#pragma unroll
+          for (int i = 0; i < 16; ++i) col[i] += (i == id) ? v : 0.f;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) W[i + kSumsLdw * c] = col[i];
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < mo4; c0 += 4) {
+      const int c = c0 + kq;
+      const float wv = W[r16 + kSumsLdw * c];
+      const int cb = cbase[c];
+      const float yv = (r16 < mr && cb >= 0) ? ys[cb + r16 * stride[mode]] : 0.f;
+      accA = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, wv, accA, 0, 0, 0);
+      accB = __builtin_amdgcn_mfma_f32_16x16x4f32(yv, wv, accB, 0, 0, 0);
+    }
+  }
+  // tile element (4 kq + v, r16): A[i][j] with i = 4 kq + v, j = r16; B[p][j] likewise
+  const int nent = na * na + mr * na;
+  double* row = part + (size_t)blockIdx.x * nent;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * kq + v, j = r16;
+    if (i < na && j < na) row[i + na * j] = (double)accA[v];
+    if (i < mr && j < na) row[na * na + i + mr * j] = (double)accB[v];
+  }
+}
+
 template <typename T>
 __global__ void tensor_rescale_kernel(int64_t n_el, int div, int na, const int32_t* supp, T* coef, const double* w) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -474,9 +585,25 @@ hipError_t launch_tensor_omp(const TensorArgs<T>& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+bool tensor_sums_mfma_ok(int nmodes, const int* m, const int* n, int mode) {
+  return n[mode] <= 16 && m[mode] <= 16 && sums_mfma_lds_bytes(nmodes, m, n, mode) <= 64 * 1024;
+}
+
 template <typename T>
 hipError_t launch_tensor_sums(const TensorArgs<T>& a, int mode, double* part, hipStream_t st) {
   const int rows = tensor_sums_rows(a.N);
+  if constexpr (sizeof(T) == 4) {
+    if (tensor_sums_mfma_ok(a.nmodes, a.m, a.n, mode)) {
+      const size_t lds = sums_mfma_lds_bytes(a.nmodes, a.m, a.n, mode);
+      if (a.nmodes == 2)
+        hipLaunchKernelGGL((tensor_sums_mfma_kernel<2>), dim3((unsigned)rows), dim3(kWave), lds, st, a, mode, part);
+      else if (a.nmodes == 3)
+        hipLaunchKernelGGL((tensor_sums_mfma_kernel<3>), dim3((unsigned)rows), dim3(kWave), lds, st, a, mode, part);
+      else
+        hipLaunchKernelGGL((tensor_sums_mfma_kernel<4>), dim3((unsigned)rows), dim3(kWave), lds, st, a, mode, part);
+      return hipGetLastError();
+    }
+  }
   const size_t lds = sums_lds_bytes(a.nmodes, a.m, a.n, mode, sizeof(T));
   if (a.nmodes == 2)
     hipLaunchKernelGGL((tensor_sums_kernel<T, 2>), dim3((unsigned)rows), dim3(kWave), lds, st, a, mode, part);
