@@ -445,7 +445,9 @@ def tensor_workload(api, synth):
             **support_agreement(pc.supp[:nsub].cpu().numpy(), so),
             "code_ms": code_s * 1e3, "code_tflops": flops / code_s / 1e12,
             "code_frac_fp32": flops / code_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
-            "code_kernel": "tensor_omp_kernel<float, 3> (one wave per signal, all in LDS)"}
+            "code_kernel": "omp_wave_mfma_kernel<WCfg<8, 32, 12, 72, 8, ...>> (modes 2 and 3 collapsed into one "
+                           "Kronecker factor: 8 x 32 signals, 12 x 72 atoms)",
+            "sums_kernel": "tensor_sums_mfma_kernel<3> (16x16x4 FP32 MFMA over the concatenated W and Y)"}
 
 
 def uneven_workload(api, oracle, synth):

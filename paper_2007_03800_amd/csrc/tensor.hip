@@ -567,7 +567,8 @@ size_t tensor_sums_lds(int nmodes, const int* m, const int* n, int mode, size_t 
 }
 
 int tensor_sums_rows(int64_t N) {
-  int64_t r = N < 1024 ? N : 1024;
+  // one wave per row: enough rows for several waves per SIMD
+  int64_t r = N < 4096 ? N : 4096;
   return (int)(r < 1 ? 1 : r);
 }
 
