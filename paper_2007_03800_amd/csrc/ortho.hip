@@ -34,6 +34,61 @@ __device__ inline T sig_load(const OmpArgs<T>& a, int64_t e) {
   return a.Y[e];
 }
 
+// Cross-lane moves inside a row of 16 lanes by DPP (no LDS round trip): quad swaps (lane xor 1,
+// xor 2), half-row mirror (lane i <-> 7 - i within each 8) and row mirror (i <-> 15 - i).  After
+// the four steps of a commutative, associative combine every lane of the row holds the row's
+// result.
+constexpr int kDppX1 = 0xB1, kDppX2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int CTRL>
+__device__ inline int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, typename U>
+__device__ inline U dpp_move(U v) {
+  if constexpr (sizeof(U) == 4) {
+    return __builtin_bit_cast(U, dpp_int<CTRL>(__builtin_bit_cast(int, v)));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_int<CTRL>((int)(b & 0xffffffffll)), hi = dpp_int<CTRL>((int)(b >> 32));
+    return __builtin_bit_cast(U, ((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+template <typename U>
+__device__ inline U row16_sum(U v) {
+  v += dpp_move<kDppX1>(v);
+  v += dpp_move<kDppX2>(v);
+  v += dpp_move<kDppHalfMirror>(v);
+  v += dpp_move<kDppMirror>(v);
+  return v;
+}
+// (value, index) maximum over the row, ties to the smaller index
+template <int CTRL, typename U>
+__device__ inline void argmax_step(U& v, int& idx) {
+  const U ov = dpp_move<CTRL>(v);
+  const int oi = dpp_int<CTRL>(idx);
+  const bool take = ov > v || (ov == v && oi < idx);
+  v = take ? ov : v;
+  idx = take ? oi : idx;
+}
+template <typename U>
+__device__ inline void row16_argmax(U& v, int& idx) {
+  argmax_step<kDppX1>(v, idx);
+  argmax_step<kDppX2>(v, idx);
+  argmax_step<kDppHalfMirror>(v, idx);
+  argmax_step<kDppMirror>(v, idx);
+}
+template <typename U>
+__device__ inline U lane_value(U v, int k) {  // value of lane k (k uniform)
+  if constexpr (sizeof(U) == 4) {
+    return __builtin_bit_cast(U, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __builtin_bit_cast(U, ((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kWave* kOWaves) ortho_code_kernel(OmpArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -93,15 +148,8 @@ __global__ void __launch_bounds__(kWave* kOWaves) ortho_code_kernel(OmpArgs<T> a
         best = ok ? m : best;
         ba = ok ? e : ba;
       }
-      // across the signal's 16 lanes
-#pragma unroll
-      for (int o = 1; o < kOLanes; o <<= 1) {
-        const T ob = __shfl_xor(best, o, kWave);
-        const int oa = __shfl_xor(ba, o, kWave);
-        const bool take = ob > best || (ob == best && oa < ba);
-        best = take ? ob : best;
-        ba = take ? oa : ba;
-      }
+      // across the signal's 16 lanes (one DPP row)
+      row16_argmax(best, ba);
       // the owner lane marks it and provides the signed value
       T val = 0;
       if (ba != INT_MAX && ba % kOLanes == l) {
@@ -110,8 +158,7 @@ __global__ void __launch_bounds__(kWave* kOWaves) ortho_code_kernel(OmpArgs<T> a
         for (int uu = 0; uu < kOMaxPer; ++uu) val = uu == u ? cv[uu] : val;
         taken |= 1u << u;
       }
-#pragma unroll
-      for (int o = 1; o < kOLanes; o <<= 1) val += __shfl_xor(val, o, kWave);  // only the owner is nonzero
+      val = row16_sum(val);  // only the owner is nonzero
       if (valid && l == 0) {
         a.supp[k * s + t] = ba == INT_MAX ? -1 : ba;
         a.coef[k * s + t] = ba == INT_MAX ? T(0) : val;
@@ -134,8 +181,7 @@ __global__ void __launch_bounds__(kWave* kOWaves) ortho_code_kernel(OmpArgs<T> a
       }
       rr += r * r;
     }
-#pragma unroll
-    for (int o = 1; o < kOLanes; o <<= 1) rr += __shfl_xor(rr, o, kWave);
+    rr = row16_sum(rr);
     if (valid && l == 0 && a.res2) a.res2[k] = rr;
     wave_sync();
   }
@@ -175,12 +221,14 @@ __global__ void __launch_bounds__(kWave) procrustes_kernel(const double* __restr
           pb = wj * wj;
           pg = wi * wj;
         }
-        // sums over the rows in a fixed butterfly order: every lane ends with the same totals
-        for (int o = 1; o < kWave; o <<= 1) {
-          pa += __shfl_xor(pa, o, kWave);
-          pb += __shfl_xor(pb, o, kWave);
-          pg += __shfl_xor(pg, o, kWave);
-        }
+        // sums over the n <= 32 rows in a fixed order: each 16-lane row by DPP, then rows 0 and
+        // 1 added from their first lanes (uniform values: every lane takes the same decision)
+        pa = row16_sum(pa);
+        pb = row16_sum(pb);
+        pg = row16_sum(pg);
+        pa = n > 16 ? lane_value(pa, 0) + lane_value(pa, 16) : lane_value(pa, 0);
+        pb = n > 16 ? lane_value(pb, 0) + lane_value(pb, 16) : lane_value(pb, 0);
+        pg = n > 16 ? lane_value(pg, 0) + lane_value(pg, 16) : lane_value(pg, 0);
         if (fabs(pg) <= 1e-15 * sqrt(pa * pb) || pg == 0.0) continue;
         rotated = 1;
         const double zeta = (pb - pa) / (2.0 * pg);
