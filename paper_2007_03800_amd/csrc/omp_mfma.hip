@@ -169,7 +169,7 @@ __device__ inline void sums_epilogue(f32x4* acc, float* tc, const float* ys, con
     for (int j = 0; j < TPX; ++j) acc[(TPX * TPX + i * TPX + j) * kWave] = accR[i][j];
 }
 
-template <class C>
+template <class C, bool ORTHO = false>
 __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE)))
     omp_mfma_kernel(OmpArgs<float> a) {
   constexpr int M1 = C::M1, M2 = C::M2, N1 = C::N1, N2 = C::N2, S = C::S;
@@ -290,14 +290,71 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
       }
     }
 
-    // ---- greedy loop
-    float* L = sWork[wv] + g * C::NLP;
-    float dinv[S], x[S];
+    float x[S];
     int ia[S], ja[S];
 #pragma unroll
-    for (int k = 0; k < S; ++k) { x[k] = 0.f; ia[k] = 0; ja[k] = 0; dinv[k] = 0.f; }
-    bool active = valid;
+    for (int k = 0; k < S; ++k) { x[k] = 0.f; ia[k] = 0; ja[k] = 0; }
     int nsel = 0;
+    if constexpr (ORTHO) {
+      // ---- Remark 1's codes: the s largest |C| in decreasing order (ties: smaller atom), exact.
+      // Key of an element: its |C| bits above 16 bits holding 65535 - atom, compared as 64-bit
+      // integers; chosen elements drop out through the lane's taken mask.
+      unsigned taken = 0u;
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int bj = 0; bj < TJ; ++bj)
+#pragma unroll
+          for (int bi = 0; bi < TI; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int e = (bj * TI + bi) * 4 + v;
+              const float cv = al[bi * TJ + bj][v];  // by value
+              const int atom = (4 * bi + v) + N1 * (4 * bj + c);
+              const unsigned long long key =
+                  ((unsigned long long)(__float_as_uint(cv) & 0x7FFFFFFFu) << 16) | (unsigned)(0xFFFF - atom);
+              const bool ok = !((taken >> e) & 1u) && key > best;
+              best = ok ? key : best;
+            }
+        // the signal's four lanes: quad swaps on both halves of the key
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          const unsigned lo = (unsigned)best, hi = (unsigned)(best >> 32);
+          const unsigned olo = (unsigned)(o == 0 ? dpp_x1((int)lo) : dpp_x2((int)lo));
+          const unsigned ohi = (unsigned)(o == 0 ? dpp_x1((int)hi) : dpp_x2((int)hi));
+          const unsigned long long ok = ((unsigned long long)ohi << 32) | olo;
+          best = ok > best ? ok : best;
+        }
+        const int atom = 0xFFFF - (int)(best & 0xFFFFull);
+        const int it = atom % N1, jt = atom / N1;
+        const int eo = ((jt / 4) * TI + it / 4) * 4 + it % 4;  // element index in the owner lane
+        const bool owner = (jt % 4) == c;
+        float val = 0.f;
+#pragma unroll
+        for (int bj = 0; bj < TJ; ++bj)
+#pragma unroll
+          for (int bi = 0; bi < TI; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int e = (bj * TI + bi) * 4 + v;
+              const float cv = al[bi * TJ + bj][v];
+              val = (owner && e == eo) ? cv : val;
+            }
+        taken |= owner ? (1u << eo) : 0u;
+        val = quad_sum(val);  // only the owner's value is nonzero
+        x[t] = val;
+        ia[t] = it;
+        ja[t] = jt;
+      }
+      nsel = valid ? S : 0;
+    } else {
+    // ---- greedy loop
+    float* L = sWork[wv] + g * C::NLP;
+    float dinv[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) dinv[k] = 0.f;
+    bool active = valid;
     const float stop_thr = stop_rel * ynorm;
 
 #pragma unroll
@@ -447,6 +504,7 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
       }
       // no wave sync here: each lane reads back only the L rows it wrote itself
     }
+    }  // greedy loop
 
     // ---- explicit residual and outputs
     float rr = 0.f;
@@ -557,6 +615,48 @@ MfmaVariant mfma_variants_table[] = {
 const int mfma_variants_count = sizeof(mfma_variants_table) / sizeof(mfma_variants_table[0]);
 
 int64_t mfma_partial_rows(int64_t N, int wpe) { return mfma_blocks(N, wpe); }
+
+// Remark 1's orthonormal variant on the same layout: first correlation on the matrix cores,
+// exact top-s selection, explicit residual, and the update sums in the epilogue (the B block
+// is what the Procrustes update reads).  (m1, m2, s, waves per SIMD); n1 = m1, n2 = m2.
+#define SDL_ORTHO_MFMA_VARIANTS(X) X(8, 8, 8, 2)
+
+struct OrthoMfmaVariant {
+  int m1, m2, s, wpe;
+  hipError_t (*launch)(const OmpArgs<float>&, hipStream_t);
+};
+
+template <class C>
+hipError_t launch_ortho_cfg(const OmpArgs<float>& a, hipStream_t st) {
+  const int64_t blocks = mfma_blocks(a.N, C::WPE);
+  hipLaunchKernelGGL((omp_mfma_kernel<C, true>), dim3((unsigned)blocks), dim3(kWave * kWaves), 0, st, a);
+  return hipGetLastError();
+}
+
+const OrthoMfmaVariant kOrthoMfma[] = {
+#define X(A_, B_, S_, W_) {A_, B_, S_, W_, &launch_ortho_cfg<MCfg<A_, B_, A_, B_, S_, W_>>},
+    SDL_ORTHO_MFMA_VARIANTS(X)
+#undef X
+};
+
+bool ortho_mfma_supported(int m1, int m2, int n1, int n2, int s) {
+  for (const OrthoMfmaVariant& v : kOrthoMfma)
+    if (v.m1 == m1 && v.m2 == m2 && n1 == m1 && n2 == m2 && v.s == s) return true;
+  return false;
+}
+
+int64_t ortho_mfma_partial_rows(int64_t N, int m1, int m2, int s) {
+  for (const OrthoMfmaVariant& v : kOrthoMfma)
+    if (v.m1 == m1 && v.m2 == m2 && v.s == s) return mfma_blocks(N, v.wpe);
+  return 0;
+}
+
+hipError_t launch_ortho_mfma(const OmpArgs<float>& a, hipStream_t st) {
+  if (a.N == 0) return hipSuccess;
+  for (const OrthoMfmaVariant& v : kOrthoMfma)
+    if (v.m1 == a.m1 && v.m2 == a.m2 && a.n1 == a.m1 && a.n2 == a.m2 && v.s == a.s) return v.launch(a, st);
+  return hipErrorInvalidValue;
+}
 
 void mfma_set_cus(int n) {
   if (n > 0) g_cus = n;

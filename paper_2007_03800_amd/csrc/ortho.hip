@@ -189,8 +189,9 @@ __global__ void __launch_bounds__(kWave* kOWaves) ortho_code_kernel(OmpArgs<T> a
 
 // One wave: the last stage of the fixed-order reduction of the partial rows (row stride ld),
 // then the polar factor of B (the n x n block of the sums after A) by one-sided Jacobi
-// rotations (lane x holds row x; pairs of columns in cyclic row order, as the oracle), and the
-// new dictionary D = U V^T with its compute-type copy and Gram matrix.  A rank-deficient B
+// rotations (n <= 8: four disjoint column pairs at a time in round-robin order; larger n: lane x
+// holds row x, pairs in cyclic row order as the oracle), and the new dictionary D = U V^T with
+// its compute-type copy and Gram matrix.  A rank-deficient B
 // leaves the dictionary unchanged and sets the singular status.
 template <typename T>
 __global__ void __launch_bounds__(kWave) procrustes_kernel(const double* __restrict__ src, int nrow, int ld, int n,
@@ -210,7 +211,64 @@ __global__ void __launch_bounds__(kWave) procrustes_kernel(const double* __restr
   }
   wave_sync();
   const bool row = x < n;
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  if (n <= 8) {
+    // Up to four disjoint column pairs rotated at once (round-robin order: n' - 1 rounds of n' / 2
+    // pairs cover every pair once per sweep, n' = n rounded up to even, pairs with the dummy
+    // column n skipped); lane 8 q + r holds row r for the q-th pair of the round.  The polar
+    // factor is unique for a full-rank B, so the order of the rotations changes only rounding.
+    const int np = n + (n & 1), q = x / 8, r = x % 8;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      bool rotated = false;
+      for (int round = 0; round < np - 1; ++round) {
+        int i = -1, j = -1;
+        if (q < np / 2) {
+          if (q == 0) {
+            i = np - 1;
+            j = round;
+          } else {
+            i = (round + q) % (np - 1);
+            j = (round - q + np - 1) % (np - 1);
+          }
+          if (i > j) { const int tmp = i; i = j; j = tmp; }
+        }
+        const bool act = j >= 0 && j < n;  // a real pair (the dummy column is n)
+        double pa = 0.0, pb = 0.0, pg = 0.0;
+        if (act && r < n) {
+          const double wi = W[r + n * i], wj = W[r + n * j];
+          pa = wi * wi;
+          pb = wj * wj;
+          pg = wi * wj;
+        }
+        // sums over the pair's eight lanes (quad swaps and the half-row mirror)
+        pa += dpp_move<kDppX1>(pa);
+        pb += dpp_move<kDppX1>(pb);
+        pg += dpp_move<kDppX1>(pg);
+        pa += dpp_move<kDppX2>(pa);
+        pb += dpp_move<kDppX2>(pb);
+        pg += dpp_move<kDppX2>(pg);
+        pa += dpp_move<kDppHalfMirror>(pa);
+        pb += dpp_move<kDppHalfMirror>(pb);
+        pg += dpp_move<kDppHalfMirror>(pg);
+        const bool rot = act && !(fabs(pg) <= 1e-15 * sqrt(pa * pb) || pg == 0.0);
+        if (rot) {
+          const double zeta = (pb - pa) / (2.0 * pg);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          if (r < n) {
+            const double wi = W[r + n * i], wj = W[r + n * j];
+            W[r + n * i] = c * wi - sn * wj;
+            W[r + n * j] = sn * wi + c * wj;
+            const double vi = V[r + n * i], vj = V[r + n * j];
+            V[r + n * i] = c * vi - sn * vj;
+            V[r + n * j] = sn * vi + c * vj;
+          }
+        }
+        rotated = rotated || rot;
+        wave_sync();
+      }
+      if (__ballot(rotated) == 0ull) break;
+    }
+  } else for (int sweep = 0; sweep < 60; ++sweep) {
     int rotated = 0;
     for (int i = 0; i < n - 1; ++i)
       for (int j = i + 1; j < n; ++j) {

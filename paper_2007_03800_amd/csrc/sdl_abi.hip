@@ -417,7 +417,14 @@ int run_omp(const sdl_problem& r, const PBuf& b, const Opt& o, const Plan& pl, i
   a.sums_side = sums_side;
   a.sums_part = b.part;
   if (o.method == 1) {
-    if (sums_side != 0) return fail(SDL_E_UNSUPPORTED, "the orthonormal variant has no fused sums");
+    if constexpr (sizeof(T) == 4) {
+      if (ortho_mfma_supported(r.m1, r.m2, r.n1, r.n2, r.s)) {
+        SDL_TRY(L.begin(0));
+        HIP_TRY(launch_ortho_mfma(a, L.st));
+        return L.end();
+      }
+    }
+    if (sums_side != 0) return fail(SDL_E_UNSUPPORTED, "no fused sums for the orthonormal variant at this shape");
     SDL_TRY(L.begin(0));
     HIP_TRY(launch_ortho_code<T>(a, L.st));
     return L.end();
@@ -821,6 +828,15 @@ int iterate_problem(sdl_problem* p, int q, int K, const Opt& o, const Plan& pl, 
       SDL_TRY(run_reduce_solve<T>(1, r, b, pl, rows, true, q, K, L));
       SDL_TRY(run_omp<T>(r, b, o, pl, 2, L));
       SDL_TRY(run_reduce_solve<T>(2, r, b, pl, rows, true, -1, K, L));
+    } else if (o.method == 1 && o.schedule == 0 && sizeof(T) == 4 &&
+               ortho_mfma_supported(r.m1, r.m2, r.n1, r.n2, r.s)) {
+      // Remark 1's variant with the B sums of each Procrustes update in the coding epilogue
+      const int rows = (int)ortho_mfma_partial_rows(r.N, r.m1, r.m2, r.s);
+      SDL_TRY(run_omp<T>(r, b, o, pl, 1, L));
+      SDL_TRY(run_rmse<T>(r, b, pl, q, K, L));
+      SDL_TRY(run_reduce_solve<T>(1, r, b, pl, rows, true, -1, K, L, 1));
+      SDL_TRY(run_omp<T>(r, b, o, pl, 2, L));
+      SDL_TRY(run_reduce_solve<T>(2, r, b, pl, rows, true, -1, K, L, 1));
     } else {
       SDL_TRY(run_omp<T>(r, b, o, pl, 0, L));
       SDL_TRY(run_rmse<T>(r, b, pl, q, K, L));

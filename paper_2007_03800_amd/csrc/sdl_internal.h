@@ -241,6 +241,11 @@ hipError_t launch_tensor_sums(const TensorArgs<T>& a, int mode, double* part, hi
 template <typename T>
 hipError_t launch_tensor_rescale(const TensorArgs<T>& a, int mode, const double* w, hipStream_t st);
 hipError_t tensor_init_device();
+// Remark 1's codes on the matrix-core multi-signal layout of omp_mfma.hip (FP32), with the update
+// sums of a.sums_side in the epilogue (one partial row per workgroup, ortho_mfma_partial_rows)
+bool ortho_mfma_supported(int m1, int m2, int n1, int n2, int s);
+int64_t ortho_mfma_partial_rows(int64_t N, int m1, int m2, int s);
+hipError_t launch_ortho_mfma(const OmpArgs<float>& a, hipStream_t st);
 // n-dimensional sparse coding on the two-mode one-wave kernel: the modes after the first
 // collapsed into one Kronecker factor (FP32 shapes compiled in omp_wave.hip)
 bool omp_wave_collapsed_supported(int m1, int m2, int n1, int n2, int s);
