@@ -55,7 +55,7 @@ struct MCfg {
   static constexpr int STAGE = kSigs * YS > NENTX ? kSigs * YS : NENTX;
   static_assert(N1 % 4 == 0 && N2 % 4 == 0, "4x4 tiles");
   static_assert(NT * 4 <= 64, "at most 64 correlations per lane (6-bit position in the keys)");
-  static_assert(M % 4 == 0 && M1 % 4 == 0 && M2 % kLanes == 0, "staging and 4x4 tiles of Y D2");
+  static_assert(M % 4 == 0 && M1 % 4 == 0 && M2 % 4 == 0, "staging and 4x4 tiles of Y D2 and of the residual");
 };
 
 __device__ inline void wave_sync() {
@@ -65,8 +65,8 @@ __device__ inline void wave_sync() {
 }
 
 // lane xor 1 / xor 2 inside a quad (DPP quad_perm), no LDS round trip
-__device__ inline int dpp_x1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
-__device__ inline int dpp_x2(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); }
+__device__ inline int dpp_x1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true); }
+__device__ inline int dpp_x2(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true); }
 __device__ inline float dpp_x1f(float v) { return __builtin_bit_cast(float, dpp_x1(__builtin_bit_cast(int, v))); }
 __device__ inline float dpp_x2f(float v) { return __builtin_bit_cast(float, dpp_x2(__builtin_bit_cast(int, v))); }
 __device__ inline float quad_sum(float v) {
@@ -81,10 +81,9 @@ __device__ inline unsigned umax3(unsigned a, unsigned b, unsigned c) { return ma
 
 // Epilogue of one group: the group's contribution to the next dictionary update's sums
 // (Corollary 1 for SIDE 1, Result 1 for SIDE 2), accumulated on the matrix cores.
-// Each signal's T = X D2^T (SIDE 1) or Z^T = (D1 X)^T (SIDE 2) is written column by
-// column into LDS (tc); support elements that share a row are merged in registers in
-// selection order first, so the columns are plain stores with the same sums as
-// accumulating them one element at a time.  Then P += T T^T and R^T += Yt T^T with
+// Each signal's T = X D2^T (SIDE 1) or Z^T = (D1 X)^T (SIDE 2) is built column by
+// column in LDS (tc): the lane owning a column adds every support element to its row in
+// selection order.  Then P += T T^T and R^T += Yt T^T with
 // 16x16x4 MFMA over (signal, column) pairs; acc (LDS) carries the accumulators between
 // groups.
 template <class C, int SIDE>
@@ -96,77 +95,77 @@ __device__ inline void sums_epilogue(f32x4* acc, float* tc, const float* ys, con
   constexpr int ELD = SIDE == 2 ? C::LD1 : C::LD2;
   static_assert(EMC % kLanes == 0, "columns split over the signal's lanes");
   const int r16 = lane % 16, kq = lane / 16;
-  // owner[t]: first support element with the same row atom as element t
-  int ra[S], owner[S];
+  int ra[S];
 #pragma unroll
-  for (int t = 0; t < S; ++t) {
-    ra[t] = SIDE == 1 ? ia[t] : ja[t];
-    owner[t] = t;
+  for (int t = 0; t < S; ++t) ra[t] = SIDE == 1 ? ia[t] : ja[t];
+  // NA independent accumulator sets (summed at the end): consecutive 16x16x4 MFMA then do
+  // not wait for each other's results
+  constexpr int NA = 4;
+  f32x4 accP[NA][TPX][TPX], accR[NA][TRX][TPX];
 #pragma unroll
-    for (int u = t - 1; u >= 0; --u) owner[t] = (ra[u] == ra[t]) ? u : owner[t];
+  for (int q = 0; q < NA; ++q) {
+#pragma unroll
+    for (int i = 0; i < TPX; ++i)
+#pragma unroll
+      for (int j = 0; j < TPX; ++j) accP[q][i][j] = q == 0 ? acc[(i * TPX + j) * kWave] : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < TRX; ++i)
+#pragma unroll
+      for (int j = 0; j < TPX; ++j)
+        accR[q][i][j] = q == 0 ? acc[(TPX * TPX + i * TPX + j) * kWave] : f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  f32x4 accP[TPX][TPX], accR[TRX][TPX];
-#pragma unroll
-  for (int i = 0; i < TPX; ++i)
-#pragma unroll
-    for (int j = 0; j < TPX; ++j) accP[i][j] = acc[(i * TPX + j) * kWave];
-#pragma unroll
-  for (int i = 0; i < TRX; ++i)
-#pragma unroll
-    for (int j = 0; j < TPX; ++j) accR[i][j] = acc[(TPX * TPX + i * TPX + j) * kWave];
 #pragma unroll
   for (int pass = 0; pass < kSigs; pass += C::SUB) {
     if (g >= pass && g < pass + C::SUB) {
 #pragma unroll
       for (int u2 = 0; u2 < EMC / kLanes; ++u2) {
         const int cc = c + kLanes * u2;
-        float v[S];
-#pragma unroll
-        for (int t = 0; t < S; ++t) v[t] = x[t] * Do[cc + ELD * (SIDE == 1 ? ja[t] : ia[t])];
-#pragma unroll
-        for (int t = 1; t < S; ++t)
-#pragma unroll
-          for (int u = 0; u < t; ++u) v[u] = owner[t] == u ? v[u] + v[t] : v[u];
         float* col = tc + ((g - pass) * EMC + cc) * NPX;
 #pragma unroll
         for (int r = 0; r < NPX; ++r) col[r] = 0.f;
 #pragma unroll
-        for (int t = 0; t < S; ++t)
-          if (owner[t] == t) col[ra[t]] = v[t];
+        for (int t = 0; t < S; ++t) col[ra[t]] += x[t] * Do[cc + ELD * (SIDE == 1 ? ja[t] : ia[t])];
       }
     }
     wave_sync();
-#pragma unroll 2
-    for (int kk = 0; kk < C::SUB * EMC; kk += 4) {
-      const int kx = kk + kq;
-      const int b = pass + kx / EMC, cc = kx % EMC;
-      float at[TPX], ay[TRX];
+    static_assert((C::SUB * EMC) % (4 * NA) == 0, "whole rounds of the accumulator sets");
+    for (int kk = 0; kk < C::SUB * EMC; kk += 4 * NA) {
 #pragma unroll
-      for (int i = 0; i < TPX; ++i) at[i] = tc[kx * NPX + 16 * i + r16];
+      for (int q = 0; q < NA; ++q) {
+        const int kx = kk + 4 * q + kq;
+        const int b = pass + kx / EMC, cc = kx % EMC;
+        float at[TPX], ay[TRX];
 #pragma unroll
-      for (int i = 0; i < TRX; ++i) {
-        const int row = 16 * i + r16;
-        ay[i] = row < EMR ? (SIDE == 1 ? ys[b * C::YS + cc * M1 + row] : ys[b * C::YS + cc + M1 * row]) : 0.f;
+        for (int i = 0; i < TPX; ++i) at[i] = tc[kx * NPX + 16 * i + r16];
+#pragma unroll
+        for (int i = 0; i < TRX; ++i) {
+          const int row = 16 * i + r16;
+          ay[i] = row < EMR ? (SIDE == 1 ? ys[b * C::YS + cc * M1 + row] : ys[b * C::YS + cc + M1 * row]) : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < TPX; ++i)
+#pragma unroll
+          for (int j = 0; j < TPX; ++j)
+            accP[q][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(at[i], at[j], accP[q][i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TRX; ++i)
+#pragma unroll
+          for (int j = 0; j < TPX; ++j)
+            accR[q][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ay[i], at[j], accR[q][i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < TPX; ++i)
-#pragma unroll
-        for (int j = 0; j < TPX; ++j) accP[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(at[i], at[j], accP[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < TRX; ++i)
-#pragma unroll
-        for (int j = 0; j < TPX; ++j) accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ay[i], at[j], accR[i][j], 0, 0, 0);
     }
     wave_sync();
   }
 #pragma unroll
   for (int i = 0; i < TPX; ++i)
 #pragma unroll
-    for (int j = 0; j < TPX; ++j) acc[(i * TPX + j) * kWave] = accP[i][j];
+    for (int j = 0; j < TPX; ++j)
+      acc[(i * TPX + j) * kWave] = (accP[0][i][j] + accP[1][i][j]) + (accP[2][i][j] + accP[3][i][j]);
 #pragma unroll
   for (int i = 0; i < TRX; ++i)
 #pragma unroll
-    for (int j = 0; j < TPX; ++j) acc[(TPX * TPX + i * TPX + j) * kWave] = accR[i][j];
+    for (int j = 0; j < TPX; ++j)
+      acc[(TPX * TPX + i * TPX + j) * kWave] = (accR[0][i][j] + accR[1][i][j]) + (accR[2][i][j] + accR[3][i][j]);
 }
 
 template <class C, bool ORTHO = false>
@@ -507,16 +506,36 @@ __global__ void __launch_bounds__(kWave* kWaves) __attribute__((amdgpu_waves_per
     }  // greedy loop
 
     // ---- explicit residual and outputs
+    // D1 X D2^T on the matrix cores: S rank-one terms x_k d1_{i_k} d2_{j_k}^T per 4x4 tile
+    // (register v of tile (bp, bq) in lane c: row 4bp + v, column 4bq + c); unused slots add 0
+    f32x4 dx[M1 / 4][M2 / 4];
+#pragma unroll
+    for (int bp = 0; bp < M1 / 4; ++bp)
+#pragma unroll
+      for (int bq = 0; bq < M2 / 4; ++bq) dx[bp][bq] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      float av[M1 / 4], bv[M2 / 4];
+#pragma unroll
+      for (int bp = 0; bp < M1 / 4; ++bp) av[bp] = x[k] * sD1[(4 * bp + c) + C::LD1 * ia[k]];
+#pragma unroll
+      for (int bq = 0; bq < M2 / 4; ++bq) bv[bq] = sD2[(4 * bq + c) + C::LD2 * ja[k]];
+#pragma unroll
+      for (int bp = 0; bp < M1 / 4; ++bp)
+#pragma unroll
+        for (int bq = 0; bq < M2 / 4; ++bq)
+          dx[bp][bq] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[bp], bv[bq], dx[bp][bq], 0, 0, 0);
+    }
     float rr = 0.f;
 #pragma unroll
-    for (int u = 0; u < M / kLanes; ++u) {
-      const int e = c * (M / kLanes) + u;
-      const int p = e % M1, q = e / M1;
-      float r = y[e];
+    for (int bp = 0; bp < M1 / 4; ++bp)
 #pragma unroll
-      for (int k = 0; k < S; ++k) r -= x[k] * sD1[p + C::LD1 * ia[k]] * sD2[q + C::LD2 * ja[k]];
-      rr += r * r;
-    }
+      for (int bq = 0; bq < M2 / 4; ++bq)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float r = y[(4 * bp + v) + M1 * (4 * bq + c)] - dx[bp][bq][v];
+          rr += r * r;
+        }
     rr = quad_sum(rr);
     if (valid) {
       const int64_t k = a.index ? (int64_t)a.index[k0 + g] : k0 + g;
