@@ -64,18 +64,6 @@ struct WCfg {
 constexpr int trow(int k) { return k * (k + 1) / 2; }  // row k of packed L^{-1}
 
 template <typename U>
-__device__ inline U bcast(U v, int k) {  // value of lane k (k uniform)
-  if constexpr (sizeof(U) == 4) {
-    return __builtin_bit_cast(U, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
-  } else {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-    return __builtin_bit_cast(U, ((long long)hi << 32) | (unsigned int)lo);
-  }
-}
-
-template <typename U>
 __device__ inline U wave_sum(U v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -332,12 +320,16 @@ __global__ void __launch_bounds__(kWave* C::WPB)
         }
       }
     }
-    // explicit residual Y - sum_q x_q d1_{i_q} d2_{j_q}^T
+    // explicit residual Y - sum_q x_q d1_{i_q} d2_{j_q}^T, the support read back from LDS
+    // (coefficients staged in the exchange vector, atoms in supi / supj)
+    wave_sync();
+    if (lane < t) xg[lane] = my_x;
+    wave_sync();
     T rr = 0;
     for (int e = lane; e < M; e += kWave) {
       const int p = e % M1, q = e / M1;
       T r = ys[e];
-      for (int u = 0; u < t; ++u) r -= bcast(my_x, u) * sD1[p + M1 * bcast(my_i, u)] * sD2[q + M2 * bcast(my_j, u)];
+      for (int u = 0; u < t; ++u) r -= xg[u] * sD1[p + M1 * (int)supi[u]] * sD2[q + M2 * (int)supj[u]];
       rr += r * r;
     }
     rr = wave_sum(rr);
@@ -698,15 +690,52 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
         }
       }
     }
-    // explicit residual Y - sum_q x_q d1_{i_q} d2_{j_q}^T
-    float rr = 0.f;
-    for (int e = lane; e < M; e += kWave) {
-      const int p = e % M1, q = e / M1;
-      float r = ysT[q + YQ * p];
-      for (int u = 0; u < t; ++u)
-        r -= bcast(my_x, u) * sD1T[bcast(my_i, u) + P1 * p] * sD2T[bcast(my_j, u) + P2 * q];
-      rr += r * r;
+    // explicit residual Y - D1_S diag(x) D2_S^T on the matrix cores: four support terms per
+    // 16x16x4 MFMA (terms beyond t have x = 0; support atoms beyond t are atom 0)
+    wave_sync();
+    if (lane < SP) xg[lane] = lane < t ? my_x : 0.f;
+    wave_sync();
+    constexpr int RP = (M1 + 15) / 16;
+    f32x4 dx[RP][TQ];
+#pragma unroll
+    for (int tp = 0; tp < RP; ++tp)
+#pragma unroll
+      for (int tq = 0; tq < TQ; ++tq) dx[tp][tq] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int u0 = 0; u0 < t; u0 += 4) {
+      const int u = u0 + k4;
+      const float xu = xg[u];
+      const int iu = (int)supi[u], ju = (int)supj[u];
+      float av[RP], bv[TQ];
+#pragma unroll
+      for (int tp = 0; tp < RP; ++tp) {
+        const int p = 16 * tp + r16;
+        av[tp] = p < M1 ? xu * sD1T[iu + P1 * p] : 0.f;
+      }
+#pragma unroll
+      for (int tq = 0; tq < TQ; ++tq) {
+        const int q = 16 * tq + r16;
+        bv[tq] = q < M2 ? sD2T[ju + P2 * q] : 0.f;
+      }
+#pragma unroll
+      for (int tp = 0; tp < RP; ++tp)
+#pragma unroll
+        for (int tq = 0; tq < TQ; ++tq)
+          dx[tp][tq] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tp], bv[tq], dx[tp][tq], 0, 0, 0);
     }
+    float rr = 0.f;
+#pragma unroll
+    for (int tp = 0; tp < RP; ++tp)
+#pragma unroll
+      for (int tq = 0; tq < TQ; ++tq)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int p = 16 * tp + 4 * k4 + v, q = 16 * tq + r16;
+          if (p < M1 && q < M2) {
+            const float r = ysT[q + YQ * p] - dx[tp][tq][v];
+            rr += r * r;
+          }
+        }
     rr = wave_sum(rr);
     if (lane < S) {
       a.supp[k * S + lane] = lane < t ? my_i + N1 * my_j : -1;

@@ -120,3 +120,21 @@ def full_size_checks(Ym, pr, s, fresh, n_each=1000, seed=11, band=1e-4, **opts):
     api.tmod_update(pu, sides=1, **opts)
     torch.cuda.synchronize()
     return len(idx), agree, ties, bad, err, float(np.abs(pu.d1() - u1).max())
+
+
+def code_residual_energy(Y, d1, d2, supp, coef, chunk=20000):
+    """FP64 energy of Y_k - sum_t coef[k, t] d1[:, i_t] d2[:, j_t]^T for every signal, from the
+    returned code itself (math layouts: Y (N, m1, m2), d1 (m1, n1), d2 (m2, n2); supp -1 = unused)."""
+    n1 = d1.shape[1]
+    out = np.empty(len(Y))
+    for k0 in range(0, len(Y), chunk):
+        k1 = min(len(Y), k0 + chunk)
+        s = supp[k0:k1]
+        valid = s >= 0
+        a = np.where(valid, s, 0)
+        c = np.where(valid, coef[k0:k1], 0.0)
+        A = np.transpose(d1[:, a % n1], (1, 2, 0)) * c[:, :, None]  # (n, S, m1)
+        B = np.transpose(d2[:, a // n1], (1, 2, 0))                  # (n, S, m2)
+        R = Y[k0:k1] - np.matmul(np.transpose(A, (0, 2, 1)), B)
+        out[k0:k1] = np.sum(R * R, axis=(1, 2))
+    return out
