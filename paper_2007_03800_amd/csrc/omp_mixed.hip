@@ -16,7 +16,9 @@
 //    operand of the second contraction D1^T V over the same rows.  The n1 x n2 correlations
 //    are produced tile by tile and never stored: each tile's values feed packed keys
 //    (|corr| with its low 8 bits replaced by the value's position in the lane) and each lane
-//    keeps its two largest keys (max3 / med3).
+//    keeps its two largest keys (max3 / med3).  Tile columns go in pairs: inside a pair the
+//    positions are constants (6 bits), and the pair's code (2 bits) joins its two largest
+//    keys before they meet the running ones, so a key costs one AND-OR.
 //  * Near-ties: let M be the signal's largest BF16 |corr|.  Every kept key within tie_band of
 //    M (at most two per lane, eight per signal) is re-scored exactly in FP32 as d1_i^T R d2_j
 //    from the FP32 residual (the signal's four lanes each contribute their rows and add by
@@ -56,7 +58,7 @@ struct XCfg {
   // over the banks); odd strides for the dictionaries
   static constexpr int YH = M + 4, LD1 = M1 + 1, LD2 = M2 + 1, NLP = NL + 1;
   static_assert(M1 % 4 == 0 && M2 % 4 == 0 && N1 % 4 == 0 && N2 % 4 == 0, "4x4 tiles");
-  static_assert(TI * TJ * 4 <= 256, "at most 256 correlations per lane (8-bit positions in the keys)");
+  static_assert(TI <= 8 && TJ <= 8, "key positions: 2 bits of tile-column pair, 6 bits inside the pair");
   static_assert(M % 4 == 0, "float4 staging");
 };
 
@@ -95,12 +97,15 @@ constexpr int tri(int k, int l) { return k * (k + 1) / 2 + l; }
 // middle of three (compiles to v_med3_u32)
 __device__ inline unsigned umed3(unsigned a, unsigned b, unsigned c) { return max(min(a, b), min(max(a, b), c)); }
 
-// atom of a packed key held by lane c of its signal
+// atom of a packed key held by lane c of its signal.  Low 8 bits of a key: (3 - pair) << 6 |
+// (63 - local), where the tile column bj = 2 pair + bl and local = (bl TI + bi) 4 + v, so larger
+// low bits mean an earlier position (ties go to the smaller position).
 template <class C>
 __device__ inline int key_atom(unsigned key, int c) {
-  const int pos = 255 - (int)(key & 0xFFu);
-  const int v = pos & 3, tile = pos >> 2;
-  const int bi = tile % C::TI, bj = min(tile / C::TI, C::TJ - 1);  // in range for any key
+  const int pair = 3 - (int)((key >> 6) & 3u), local = 63 - (int)(key & 63u);
+  const int bl = local / (4 * C::TI), rem = local % (4 * C::TI);
+  const int v = rem & 3, bi = rem >> 2;
+  const int bj = min(2 * pair + bl, C::TJ - 1);  // in range for any key
   return (4 * bi + v) + C::N1 * (4 * bj + c);
 }
 
@@ -164,38 +169,56 @@ __device__ __forceinline__ void mixed_step(Wave<C>& w, const OmpArgs<float>& a, 
 #pragma unroll
     for (int kq = 0; kq < TQ; ++kq) rop[bp][kq] = pack4(w.rt[kq][bp]);
   unsigned ka1 = 0u, ka2 = 0u, kb1 = 0u, kb2 = 0u;
-#pragma unroll 2
-  for (int bj = 0; bj < TJ; ++bj) {
-    s16x4 vop[TP];
+  // tile columns in pairs: inside a pair the keys' positions are constants; each pair keeps its
+  // own two largest keys per tracker and adds its pair code before they join the running ones
+  for (int bj0 = 0; bj0 < TJ; bj0 += 2) {
+    unsigned la1 = 0u, la2 = 0u, lb1 = 0u, lb2 = 0u;
 #pragma unroll
-    for (int bp = 0; bp < TP; ++bp) {
-      f32x4 vt = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int bl = 0; bl < 2; ++bl) {
+      const int bj = bj0 + bl;
+      if (TJ % 2 == 0 || bj < TJ) {
+        s16x4 vop[TP];
 #pragma unroll
-      for (int kq = 0; kq < TQ; ++kq)
-        vt = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(rop[bp][kq],
-                                                    __builtin_bit_cast(s16x4, sD2op[(kq * TJ + bj) * 4 + c]), vt, 0,
-                                                    0, 0);
-      vop[bp] = pack4(vt);
+        for (int bp = 0; bp < TP; ++bp) {
+          f32x4 vt = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kq = 0; kq < TQ; ++kq)
+            vt = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(rop[bp][kq],
+                                                        __builtin_bit_cast(s16x4, sD2op[(kq * TJ + bj) * 4 + c]), vt,
+                                                        0, 0, 0);
+          vop[bp] = pack4(vt);
+        }
+#pragma unroll
+        for (int bi = 0; bi < TI; ++bi) {
+          f32x4 al = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kp = 0; kp < TP; ++kp)
+            al = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(__builtin_bit_cast(s16x4, sD1op[(kp * TI + bi) * 4 + c]),
+                                                        vop[kp], al, 0, 0, 0);
+          // keys: |corr| bits, low 6 bits = 63 - (position inside the pair)
+          const unsigned e0 = (unsigned)((bl * TI + bi) * 4);
+          const unsigned k0v = (__float_as_uint(al[0]) & 0x7FFFFF00u) | (63u - e0);
+          const unsigned k1v = (__float_as_uint(al[1]) & 0x7FFFFF00u) | (62u - e0);
+          const unsigned k2v = (__float_as_uint(al[2]) & 0x7FFFFF00u) | (61u - e0);
+          const unsigned k3v = (__float_as_uint(al[3]) & 0x7FFFFF00u) | (60u - e0);
+          // two largest of {la1, la2, k0v, k1v}: the second is max(la2, med3(la1, k0v, k1v))
+          la2 = max(la2, umed3(la1, k0v, k1v));
+          la1 = max(la1, max(k0v, k1v));
+          lb2 = max(lb2, umed3(lb1, k2v, k3v));
+          lb1 = max(lb1, max(k2v, k3v));
+        }
+      }
     }
-#pragma unroll
-    for (int bi = 0; bi < TI; ++bi) {
-      f32x4 al = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kp = 0; kp < TP; ++kp)
-        al = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(__builtin_bit_cast(s16x4, sD1op[(kp * TI + bi) * 4 + c]),
-                                                    vop[kp], al, 0, 0, 0);
-      // keys: |corr| bits, low 8 bits = 255 - position (position (bj TI + bi) 4 + v)
-      const int e0 = (bj * TI + bi) * 4;
-      const unsigned k0v = (__float_as_uint(al[0]) & 0x7FFFFF00u) | (unsigned)(255 - e0);
-      const unsigned k1v = (__float_as_uint(al[1]) & 0x7FFFFF00u) | (unsigned)(254 - e0);
-      const unsigned k2v = (__float_as_uint(al[2]) & 0x7FFFFF00u) | (unsigned)(253 - e0);
-      const unsigned k3v = (__float_as_uint(al[3]) & 0x7FFFFF00u) | (unsigned)(252 - e0);
-      // two largest of {ka1, ka2, k0v, k1v}: the second is max(ka2, med3(ka1, k0v, k1v))
-      ka2 = max(ka2, umed3(ka1, k0v, k1v));
-      ka1 = max(max(ka1, k0v), k1v);
-      kb2 = max(kb2, umed3(kb1, k2v, k3v));
-      kb1 = max(max(kb1, k2v), k3v);
-    }
+    const unsigned code = (unsigned)(3 - bj0 / 2) << 6;
+    la1 |= code;
+    la2 |= code;
+    lb1 |= code;
+    lb2 |= code;
+    // two largest of the running pair and the new pair (each sorted)
+    ka2 = max(min(ka1, la1), max(ka2, la2));
+    ka1 = max(ka1, la1);
+    kb2 = max(min(kb1, lb1), max(kb2, lb2));
+    kb1 = max(kb1, lb1);
   }
   const unsigned m1 = max(ka1, kb1), m2 = max(min(ka1, kb1), max(ka2, kb2));
 
