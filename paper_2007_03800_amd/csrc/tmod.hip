@@ -30,10 +30,18 @@ __global__ void reduce_stage1_kernel(const double* __restrict__ part, int P, int
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (e >= nent) return;
-  const int b1 = (c + 1) * kChunk < P ? (c + 1) * kChunk : P;
+  const int b0 = c * kChunk, b1 = (c + 1) * kChunk < P ? (c + 1) * kChunk : P;
   double v = 0.0;
-#pragma unroll 16
-  for (int b = c * kChunk; b < b1; ++b) v += part[(size_t)b * nent + e];
+  if (b1 - b0 == kChunk) {
+    // a whole chunk: every load issued before the adds, which stay in row order
+    double q[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) q[u] = part[(size_t)(b0 + u) * nent + e];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) v += q[u];
+  } else {
+    for (int b = b0; b < b1; ++b) v += part[(size_t)b * nent + e];
+  }
   stage[(size_t)c * nent + e] = v;
 }
 
@@ -58,21 +66,36 @@ constexpr int kDirectRows = 2 * kChunk;  // up to this many partial rows the sol
 template <typename T>
 __global__ void __launch_bounds__(kSolveThreads)
     tmod_solve_kernel(const double* __restrict__ src, int nrow, int ld, double* sums, int mr, int na, double* D,
-                      T* Dc, double* G64, T* Gc, double* w, int* status, unsigned long long* counters, RmseOut r) {
+                      T* Dc, double* G64, T* Gc, double* w, int* status, unsigned long long* counters, RmseOut r,
+                      int sums_in_lds) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
+  // the reduced sums go to global memory (the caller's copy) and, when sums_in_lds, to the
+  // front of LDS, where the solve reads them
+  double* ssum = reinterpret_cast<double*>(smem_raw);
   for (int e = tid; e < ld; e += blockDim.x) {
     double v = 0.0;
-    for (int b = 0; b < nrow; ++b) v += src[(size_t)b * ld + e];
+    int b = 0;
+    for (; b + 8 <= nrow; b += 8) {  // eight loads in flight, adds in row order
+      double q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = src[(size_t)(b + u) * ld + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += q[u];
+    }
+    for (; b < nrow; ++b) v += src[(size_t)b * ld + e];
     sums[e] = v;
+    if (sums_in_lds) ssum[e] = v;
   }
   __syncthreads();
+  const double* rs = sums_in_lds ? ssum : sums;
   if (r.trace && tid == 0) {
     const int it = *r.counter;
-    r.trace[(size_t)it + r.offset] = r.denom > 0 ? sqrt(sums[r.idx] / r.denom) : 0.0;
+    r.trace[(size_t)it + r.offset] = r.denom > 0 ? sqrt(rs[r.idx] / r.denom) : 0.0;
     *r.counter = it + 1;
   }
-  solve_update_block<T>(sums, mr, na, D, Dc, G64, Gc, w, status, counters, smem_raw, tid, blockDim.x);
+  solve_update_block<T>(rs, mr, na, D, Dc, G64, Gc, w, status, counters,
+                        smem_raw + (sums_in_lds ? solve_sums_lds_bytes(ld) : 0), tid, blockDim.x);
 }
 
 // The dictionary's compute-type copy and its Gram matrix (FP64 and compute type), with D
@@ -204,8 +227,11 @@ template <typename T>
 hipError_t launch_tmod_solve(const double* src, int nrow, int ld, double* sums, int mr, int na, double* D, T* Dc,
                              double* G64, T* Gc, double* w, int* status, unsigned long long* counters,
                              const RmseOut& r, hipStream_t st) {
-  hipLaunchKernelGGL(tmod_solve_kernel<T>, dim3(1), dim3(kSolveThreads), solve_lds_bytes(na, mr), st, src, nrow, ld,
-                     sums, mr, na, D, Dc, G64, Gc, w, status, counters, r);
+  // the reduced sums stay in LDS too when they fit beside the solve's workspace
+  const size_t base = solve_lds_bytes(na, mr), with = base + solve_sums_lds_bytes(ld);
+  const int in_lds = with <= solve_lds_bytes(SDL_MAX_N, SDL_MAX_M) ? 1 : 0;
+  hipLaunchKernelGGL(tmod_solve_kernel<T>, dim3(1), dim3(kSolveThreads), in_lds ? with : base, st, src, nrow, ld,
+                     sums, mr, na, D, Dc, G64, Gc, w, status, counters, r, in_lds);
   return hipGetLastError();
 }
 

@@ -16,8 +16,11 @@ __host__ __device__ inline size_t solve_lds_bytes(int na, int mr) {
   return sizeof(double) * ((size_t)na * (na + mr + 1) + (size_t)(mr + 1) * na + na) + sizeof(int) * (na + 1) + 16;
 }
 
+// LDS bytes of ld reduced sums kept in front of the solve's workspace (16-byte multiple).
+__host__ __device__ inline size_t solve_sums_lds_bytes(int ld) { return ((size_t)ld * sizeof(double) + 15) & ~(size_t)15; }
+
 // Whole workgroup (tid = 0..nt-1).  sums = [A (na x na) | B (mr x na)], column-major,
-// A = the update's Gram sum, B = its right-hand side (global memory, written by the
+// A = the update's Gram sum, B = its right-hand side (global memory or LDS, written by the
 // caller before a block barrier).  Atoms with A_ii = 0 are used by no code: the
 // system decouples exactly and they keep their old value.  On the used set U the
 // symmetric positive definite system A_UU D*^T = B_U^T is solved by Gauss-Jordan
@@ -29,7 +32,7 @@ __host__ __device__ inline size_t solve_lds_bytes(int na, int mr) {
 // marks the sum as not positive definite: D is left unchanged and the singular
 // status bit is set.  Each solved column is then normalised (w_i = its norm; a zero
 // column keeps the old atom), and D, its compute-type copy and the Gram matrix D^T D
-// are rewritten.  smem: solve_lds_bytes(na, mr) bytes.
+// are rewritten.  smem: solve_lds_bytes(na, mr) bytes; nt a multiple of 32.
 template <typename T>
 __device__ void solve_update_block(const double* sums, int mr, int na, double* D, T* Dc, double* G64, T* Gc,
                                    double* w, int* status, unsigned long long* counters, unsigned char* smem,
@@ -64,6 +67,10 @@ __device__ void solve_update_block(const double* sums, int mr, int na, double* D
   }
   __syncthreads();
   bool bad = false;
+  // thread tid updates rows i = tid / kGJCols (+ multiples of nt / kGJCols) at columns
+  // c = tid % kGJCols (+ multiples of kGJCols): no index division inside the steps
+  constexpr int kGJCols = 32;
+  const int ci = tid % kGJCols, ri = tid / kGJCols, rstep = nt / kGJCols;
   for (int k = 0; k < nu; ++k) {
     const double piv = M[k * ldm + k];
     if (!(piv > kSpdRelTol * diag0[k])) {  // same value in every thread: uniform exit
@@ -71,27 +78,29 @@ __device__ void solve_update_block(const double* sums, int mr, int na, double* D
       break;
     }
     const double inv = 1.0 / piv;
-    const int rem = ncol - k - 1;  // columns right of k
-    for (int e = tid; e < nu * rem; e += nt) {
-      const int i = e / rem, c = k + 1 + e % rem;
-      if (i != k) M[i * ldm + c] -= M[i * ldm + k] * inv * M[k * ldm + c];
+    for (int i = ri; i < nu; i += rstep) {
+      if (i == k) continue;
+      const double f = M[i * ldm + k] * inv;
+      for (int c = k + 1 + ci; c < ncol; c += kGJCols) M[i * ldm + c] -= f * M[k * ldm + c];
     }
     __syncthreads();
   }
   if (!bad) {
-    // row k now reads [pivot_k e_k | pivot_k * (D*^T)_k]: normalise each solved atom
-    for (int k = tid; k < nu; k += nt) {
+    // row k now reads [pivot_k e_k | pivot_k * (D*^T)_k]: normalise each solved atom, one
+    // thread per entry (k, p), each forming the atom's norm itself
+    for (int e = tid; e < nu * mr; e += nt) {
+      const int k = e / mr, p = e % mr;
       const double inv = 1.0 / M[k * ldm + k];
       double nrm = 0.0;
-      for (int p = 0; p < mr; ++p) {
-        const double v = M[k * ldm + nu + p] * inv;
+      for (int q = 0; q < mr; ++q) {
+        const double v = M[k * ldm + nu + q] * inv;
         nrm += v * v;
       }
       nrm = sqrt(nrm);
       if (nrm > 0.0) {
         const int i = U[k];
-        w[i] = nrm;
-        for (int p = 0; p < mr; ++p) Dn[p + ldd * i] = (M[k * ldm + nu + p] * inv) / nrm;
+        if (p == 0) w[i] = nrm;
+        Dn[p + ldd * i] = (M[k * ldm + nu + p] * inv) / nrm;
       }
     }
   } else if (tid == 0) {
