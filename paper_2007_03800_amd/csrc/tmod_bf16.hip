@@ -98,8 +98,11 @@ __global__ void __launch_bounds__(kWave* kBWaves) tmod_sums_bf16_kernel(TmodArgs
   for (int64_t bi = w; bi < nbatch; bi += kBWaves) {
     const int64_t kb = k0 + bi * bs;
     const int nb = (int)((k1 - kb) < bs ? (k1 - kb) : bs);
+    // codes: atom a = i + n1 j split once per batch into this side's (row | other << 16), -1 unused
     for (int e = lane; e < nb * S; e += kWave) {
-      cidx[e] = a.supp[kb * S + e];
+      const int at = a.supp[kb * S + e];
+      const int i = at % n1, j = at / n1;
+      cidx[e] = at < 0 ? -1 : (side == 1 ? (i | (j << 16)) : (j | (i << 16)));
       cval[e] = a.coef[kb * S + e];
     }
     // Tcat starts at zero (rows no code touches stay zero)
@@ -113,25 +116,26 @@ __global__ void __launch_bounds__(kWave* kBWaves) tmod_sums_bf16_kernel(TmodArgs
         int ra[S];
 #pragma unroll
         for (int t = 0; t < S; ++t) {
-          const int at = cidx[b * S + t];
-          const int atc = at < 0 ? 0 : at;
-          const int i = atc % n1, j = atc / n1;
-          ra[t] = at < 0 ? -1 : (side == 1 ? i : j);
-          v[t] = at < 0 ? 0.f : cval[b * S + t] * Do[c + mc * (side == 1 ? j : i)];
+          const int pk = cidx[b * S + t];
+          ra[t] = pk < 0 ? -1 : (pk & 0xFFFF);
+          v[t] = pk < 0 ? 0.f : cval[b * S + t] * Do[c + mc * (pk < 0 ? 0 : (pk >> 16))];
         }
-        // codes that share a row are added in selection order into the first one
+        // codes that share a row add up in selection order into the row's first code (later
+        // ones of the row also collect partial sums, but only first occurrences are stored)
+        unsigned long long seen = 0ull;
+        bool first[S];
 #pragma unroll
-        for (int t = 1; t < S; ++t) {
-          int owner = t;
-#pragma unroll
-          for (int u = t - 1; u >= 0; --u) owner = (ra[u] == ra[t]) ? u : owner;
-#pragma unroll
-          for (int u = 0; u < t; ++u) v[u] = (owner == u) ? v[u] + v[t] : v[u];
-          ra[t] = owner == t ? ra[t] : -1;
+        for (int t = 0; t < S; ++t) {
+          first[t] = ra[t] >= 0 && !((seen >> (ra[t] & 63)) & 1ull);
+          seen |= ra[t] >= 0 ? (1ull << (ra[t] & 63)) : 0ull;
         }
+#pragma unroll
+        for (int t = 1; t < S; ++t)
+#pragma unroll
+          for (int u = 0; u < t; ++u) v[u] = ra[u] == ra[t] ? v[u] + v[t] : v[u];
 #pragma unroll
         for (int t = 0; t < S; ++t)
-          if (ra[t] >= 0) Tb[ra[t] * KP + k] = to_bf16(v[t]);
+          if (first[t]) Tb[ra[t] * KP + k] = to_bf16(v[t]);
         const int64_t yb = (kb + b) * M;
         for (int r = 0; r < mr; ++r)
           Yb[r * KP + k] = a.Yh[yb + (side == 1 ? r + a.m1 * c : c + a.m1 * r)];  // column / row c of Y_b
