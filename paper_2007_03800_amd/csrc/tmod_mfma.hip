@@ -89,9 +89,12 @@ __global__ void __launch_bounds__(kWave* kWaves) tmod_sums_kernel(TmodArgs<T> a,
   for (int64_t bi = w; bi < nbatch; bi += kWaves) {
     const int64_t kb = k0 + bi * bs;
     const int nb = (int)((k1 - kb) < bs ? (k1 - kb) : bs);
-    // the batch's codes, staged with contiguous loads
+    // the batch's codes, staged with contiguous loads; atom a = i + n1 j split once here into
+    // this side's (row | other << 16), -1 for unused slots
     for (int e = lane; e < nb * s; e += kWave) {
-      cidx[e] = a.supp[kb * s + e];
+      const int at = a.supp[kb * s + e];
+      const int i = at % n1, j = at / n1;
+      cidx[e] = at < 0 ? -1 : (side == 1 ? (i | (j << 16)) : (j | (i << 16)));
       cval[e] = a.coef[kb * s + e];
     }
     wave_sync();
@@ -103,11 +106,9 @@ __global__ void __launch_bounds__(kWave* kWaves) tmod_sums_kernel(TmodArgs<T> a,
       for (int r = 0; r < NP; ++r) tcol[r] = T(0);
       if (b < nb) {
         for (int t = 0; t < s; ++t) {
-          const int at = cidx[b * s + t];
-          if (at < 0) continue;
-          const int i = at % n1, j = at / n1;
-          const int ra = side == 1 ? i : j, rb = side == 1 ? j : i;
-          tcol[ra] += cval[b * s + t] * Do[c + mc * rb];
+          const int pk = cidx[b * s + t];
+          if (pk < 0) continue;
+          tcol[pk & 0xFFFF] += cval[b * s + t] * Do[c + mc * (pk >> 16)];
         }
         const int64_t yb = (kb + b) * M;
         for (int r = 0; r < mr; ++r) {
