@@ -447,7 +447,8 @@ __host__ __device__ inline size_t sums_mfma_lds_bytes(int nm, const int* m, cons
     dsz += m[d] * n[d];
   }
   const int mo = M / m[mode], mo4 = (mo + 3) / 4 * 4;
-  return sizeof(float) * ((size_t)dsz + M + (size_t)kSumsLdw * mo4) + 2 * sizeof(int) * (size_t)mo4 + 32;
+  return sizeof(float) * ((size_t)dsz + M + (size_t)kSumsLdw * mo4) + 2 * sizeof(int) * (size_t)mo4 +
+         2 * sizeof(int) * SDL_MAX_S + 32;
 }
 
 template <int NM>
@@ -478,6 +479,8 @@ __global__ void __launch_bounds__(kWave) tensor_sums_mfma_kernel(TensorArgs<floa
   float* W = ys + M;  // W[i + kSumsLdw c], i < 16, c < mo4 (rows >= na and columns >= mo stay 0)
   int* cidx = reinterpret_cast<int*>(W + kSumsLdw * mo4);
   int* cbase = cidx + mo4;
+  unsigned* tpk = reinterpret_cast<unsigned*>(cbase + mo4);  // the signal's code, decoded (below)
+  float* tcv = reinterpret_cast<float*>(tpk + SDL_MAX_S);
   for (int c = lane; c < mo4; c += kWave) {
     int r = c, packed = 0, base = 0;
 #pragma unroll
@@ -496,6 +499,25 @@ __global__ void __launch_bounds__(kWave) tensor_sums_mfma_kernel(TensorArgs<floa
   for (int64_t k = blockIdx.x; k < a.N; k += gridDim.x) {
     __syncthreads();
     for (int e = lane; e < M; e += kWave) ys[e] = a.Y[k * M + e];
+    // the signal's code decoded once: slot t's atom as its per-mode indices (8 bits each) and
+    // its coefficient; an unused slot reads (0, 0) and is skipped
+    if (lane < s) {
+      const int at = a.supp[k * s + lane];
+      unsigned pk = 0u;
+      float cv = 0.f;
+      if (at >= 0) {
+        int r = at;
+#pragma unroll
+        for (int d = 0; d < nm; ++d) {
+          pk |= (unsigned)(r % n[d]) << (8 * d);
+          r /= n[d];
+        }
+        cv = a.coef[k * s + lane];
+      }
+      tpk[lane] = pk;
+      tcv[lane] = cv;
+    }
+    __syncthreads();
     for (int c = lane; c < mo4; c += kWave) {
       float col[16];
 #pragma unroll
@@ -503,14 +525,13 @@ __global__ void __launch_bounds__(kWave) tensor_sums_mfma_kernel(TensorArgs<floa
       if (c < mo) {
         const int packed = cidx[c];
         for (int t = 0; t < s; ++t) {
-          const int at = a.supp[k * s + t];
-          if (at < 0) continue;
-          int r = at, id = 0;
-          float v = a.coef[k * s + t];
+          const unsigned pk = tpk[t];
+          float v = tcv[t];
+          if (pk == 0u && v == 0.f) continue;
+          int id = 0;
 #pragma unroll
           for (int d = 0; d < nm; ++d) {
-            const int i = r % n[d];
-            r /= n[d];
+            const int i = (int)((pk >> (8 * d)) & 0xFFu);
             if (d == mode) id = i;
             else v *= Ds[d][((packed >> (8 * d)) & 0xFF) + m[d] * i];
           }
