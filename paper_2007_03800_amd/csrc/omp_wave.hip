@@ -349,11 +349,21 @@ __global__ void __launch_bounds__(kWave* C::WPB)
 // Largest (key, atom) pair of the wave, ties to the smaller atom; the result is uniform.
 // Keys are magnitudes as bit patterns (non-negative floats order like unsigned integers).
 // Within each row of 16 lanes: DPP quad swaps, half-row mirror and row mirror leave every
-// lane with its row's best; the four rows are then compared in scalar registers.
+// lane with its row's best; two DPP row broadcasts then merge the rows into lane 63.
 template <int CTRL>
 __device__ inline void argmax_dpp_stage(unsigned& key, int& atom) {
   const unsigned ok = (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, CTRL, 0xF, 0xF, false);
   const int oa = __builtin_amdgcn_update_dpp(0, atom, CTRL, 0xF, 0xF, false);
+  const bool take = ok > key || (ok == key && oa < atom);
+  key = take ? ok : key;
+  atom = take ? oa : atom;
+}
+
+// the same merge from a DPP row broadcast, in the rows of ROWS only (other rows keep theirs)
+template <int CTRL, int ROWS>
+__device__ inline void argmax_bcast_stage(unsigned& key, int& atom) {
+  const unsigned ok = (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, CTRL, ROWS, 0xF, false);
+  const int oa = __builtin_amdgcn_update_dpp(atom, atom, CTRL, ROWS, 0xF, false);
   const bool take = ok > key || (ok == key && oa < atom);
   key = take ? ok : key;
   atom = take ? oa : atom;
@@ -364,18 +374,12 @@ __device__ inline void wave_argmax_key(unsigned& key, int& atom) {
   argmax_dpp_stage<0x4E>(key, atom);   // quad_perm [2,3,0,1]
   argmax_dpp_stage<0x141>(key, atom);  // row_half_mirror
   argmax_dpp_stage<0x140>(key, atom);  // row_mirror
-  unsigned bk = (unsigned)__builtin_amdgcn_readlane((int)key, 0);
-  int ba = __builtin_amdgcn_readlane(atom, 0);
-#pragma unroll
-  for (int r = 1; r < 4; ++r) {
-    const unsigned k = (unsigned)__builtin_amdgcn_readlane((int)key, 16 * r);
-    const int at = __builtin_amdgcn_readlane(atom, 16 * r);
-    const bool take = k > bk || (k == bk && at < ba);
-    bk = take ? k : bk;
-    ba = take ? at : ba;
-  }
-  key = bk;
-  atom = ba;
+  // every lane now holds its row's best: rows 1 and 3 take in lane 15 / 47 (row_bcast:15), then
+  // rows 2 and 3 take in lane 31 (row_bcast:31), so lane 63 holds the wave's best
+  argmax_bcast_stage<0x142, 0xA>(key, atom);
+  argmax_bcast_stage<0x143, 0xC>(key, atom);
+  key = (unsigned)__builtin_amdgcn_readlane((int)key, 63);
+  atom = __builtin_amdgcn_readlane(atom, 63);
 }
 
 // FP32 variant on the matrix cores.  The n1 x n2 correlations (padded to multiples of 16)
@@ -412,6 +416,8 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
                                       float& my_x, int& my_i, int& my_j, const OmpArgs<float>& a,
                                       float& cst_out) {
   constexpr int S = C::S, SP = C::SP, NC = SP / 4;
+  // chunks of four past the support (index t and beyond) hold zeros: skip them
+  const int nc = (t + 4) / 4;
   const float gaa = g1(ia, ia) * g2(ja, ja);
   if (lane < t) xg[lane] = g1(my_i, ia) * g2(ja, my_j);
   wave_sync();
@@ -423,6 +429,7 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
   float p0 = 0.f, p1 = 0.f;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
+    if (c >= nc) break;
     const float4 r = row[c], gg = g4[c];
     p0 += r.x * gg.x;
     p1 += r.y * gg.y;
@@ -437,6 +444,7 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
   float q0 = 0.f, q1 = 0.f, v0 = 0.f, v1 = 0.f;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
+    if (c >= nc) break;
     const float4 w = w4[c], cc = col[c];
     q0 += w.x * w.x;
     q1 += w.y * w.y;
@@ -463,6 +471,7 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
     v1 = 0.f;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      if (c >= nc) break;
       const float4 w = w4[c], cc = col[c];
       v0 += cc.x * w.x;
       v1 += cc.y * w.y;
