@@ -343,7 +343,15 @@ __global__ void __launch_bounds__(kWave* C::WPB)
     }
     wave_sync();
   }
-  if (lane == 0 && n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
+  // one atomic per workgroup: atomics on one address from every wave serialise
+  __shared__ unsigned sEarly[C::WPB];
+  if (lane == 0) sEarly[wv] = n_early;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned tot = 0;
+    for (int w = 0; w < C::WPB; ++w) tot += sEarly[w];
+    if (tot) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)tot);
+  }
 }
 
 // Largest (key, atom) pair of the wave, ties to the smaller atom; the result is uniform.
@@ -389,9 +397,15 @@ __device__ inline void wave_argmax_key(unsigned& key, int& atom) {
 // for q = q0 + l / 16, i.e. one LDS read per tile row and per tile column for four terms.
 // The first correlation runs the same way in two products, W = D1^T Y (k = m1) and
 // C = W D2 (k = m2).  Padding rows and columns are zero and never selected.
-// L^{-1} is kept in square storage twice, by rows and by columns (16-byte aligned, zero
+// L^{-1} is kept twice, by rows and by columns, in float4 chunks (16-byte aligned, zero
 // outside the lower triangle of the rows written so far), so w = L^{-1} g, |w|^2 and
-// v = L^{-T} w are fixed-length float4 loops whose loads all issue at once.
+// v = L^{-T} w are float4 loops whose loads all issue at once.  For long supports
+// (s >= 24, the error-driven caps) both copies are packed: row k holds its entries
+// l < 4 (k/4 + 1), column l its entries k >= 4 (l/4), about half the LDS of square
+// storage (at s = 32 a wave's buffer drops from 10.5 KB to 5.9 KB, and LDS no longer
+// caps the waves per CU below the register limit: 6 instead of 3 per SIMD).  Shorter
+// supports keep square copies: there the packed form saves no waves and its per-lane
+// chunk bounds cost registers.
 template <class C>
 struct MLay {
   static constexpr int TR = (C::N1 + 15) / 16, TC = (C::N2 + 15) / 16, TQ = (C::M2 + 15) / 16;
@@ -401,7 +415,10 @@ struct MLay {
   static constexpr int SP = C::SP;        // multiple of 4
   static constexpr int YT = (YQ * C::M1 + 3) / 4 * 4;
   static constexpr int WSM = P1W * C::M2;
-  static constexpr int SCR = (2 * C::S + 5) * SP;  // L^{-1} by rows and by columns, gam, supi, supj, g, w
+  static constexpr int C4 = (C::S + 3) / 4;        // float4 chunks of a full row of L^{-1}
+  static constexpr bool PK = C::S >= 24;             // packed copies of L^{-1}
+  static constexpr int LPK = PK ? 8 * C4 * (C4 + 1) : C::S * SP;  // one copy (rows or columns)
+  static constexpr int SCR = 2 * LPK + 5 * SP;       // L^{-1} by rows and by columns, gam, supi, supj, g, w
   static constexpr int UNI = ((WSM > SCR ? WSM : SCR) + 3) / 4 * 4;  // W staging aliases the scratch
   static constexpr int PW = YT + UNI;
   static_assert(C::M1 % 4 == 0 && C::M2 % 4 == 0, "m1 and m2 are the k of the first-correlation MFMAs");
@@ -410,27 +427,55 @@ struct MLay {
 
 // append_atom for the square, zero-padded L^{-1} storage of the matrix-core kernel (same
 // arithmetic, same return and same visibility guarantee).
+// Offsets of the rows and columns of L^{-1}.  Packed (C4 chunks of four in a full row):
+// row k = 4c + r starts at 4 (c + 1)(2c + r), column l = 4c + r at
+// 16 (c C4 - c (c - 1) / 2) + 4 r (C4 - c) and holds entries k = 4c, 4c + 1, ...
+// Square: row k at k SP, column l at l SP, holding entries k = 0, 1, ...
+template <class Lay>
+__device__ inline int lrow(int k) {
+  if constexpr (!Lay::PK) return k * Lay::SP;
+  const int c = k >> 2, r = k & 3;
+  return 4 * (c + 1) * (2 * c + r);
+}
+template <class Lay>
+__device__ inline int lcol(int l) {
+  if constexpr (!Lay::PK) return l * Lay::SP;
+  constexpr int C4 = Lay::C4;
+  const int c = l >> 2, r = l & 3;
+  return 16 * (c * C4 - c * (c - 1) / 2) + 4 * r * (C4 - c);
+}
+// first entry index held by column l
+template <class Lay>
+__device__ inline int lcol0(int l) {
+  return Lay::PK ? 4 * (l >> 2) : 0;
+}
+
 template <class C, class G1f, class G2f>
 __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs, G1f g1, G2f g2, float* LiR,
                                       float* LiT, float* gam, float* supi, float* supj, float* xg, float* xw,
                                       float& my_x, int& my_i, int& my_j, const OmpArgs<float>& a,
                                       float& cst_out) {
-  constexpr int S = C::S, SP = C::SP, NC = SP / 4;
+  using L = MLay<C>;
+  constexpr int S = C::S, NC = L::C4;
+  constexpr bool PK = L::PK;
   // chunks of four past the support (index t and beyond) hold zeros: skip them
   const int nc = (t + 4) / 4;
   const float gaa = g1(ia, ia) * g2(ja, ja);
   if (lane < t) xg[lane] = g1(my_i, ia) * g2(ja, my_j);
   wave_sync();
-  // w = L^{-1} g in lane k < t (row k; entries past the diagonal and rows not yet
-  // written are zero, as are g and w past t)
+  // w = L^{-1} g in lane k < t (row k: its chunks c <= k/4; entries past the diagonal
+  // and rows not yet written are zero, as are g and w past t)
   const int rw = lane < S ? lane : S - 1;
-  const float4* row = reinterpret_cast<const float4*>(LiR + rw * SP);
+  const int cl = rw >> 2;  // packed: last chunk of row rw, first chunk of column rw
+  const float4* row = reinterpret_cast<const float4*>(LiR + lrow<L>(rw));
   const float4* g4 = reinterpret_cast<const float4*>(xg);
+  const float4 z4 = {0.f, 0.f, 0.f, 0.f};
   float p0 = 0.f, p1 = 0.f;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     if (c >= nc) break;
-    const float4 r = row[c], gg = g4[c];
+    // past its last chunk a row's storage holds the next rows: read in bounds, use zeros
+    const float4 r = !PK || c <= cl ? row[c] : z4, gg = g4[c];
     p0 += r.x * gg.x;
     p1 += r.y * gg.y;
     p0 += r.z * gg.z;
@@ -440,12 +485,13 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
   wave_sync();
   // |w|^2 in every lane, v = L^{-T} w in lane l < t (column l of L^{-1})
   const float4* w4 = reinterpret_cast<const float4*>(xw);
-  const float4* col = reinterpret_cast<const float4*>(LiT + rw * SP);
+  // (packed, column rw holds chunks cl, cl + 1, ...: before cl its entries are zero)
+  const float4* col = reinterpret_cast<const float4*>(LiT + lcol<L>(rw) - lcol0<L>(rw));
   float q0 = 0.f, q1 = 0.f, v0 = 0.f, v1 = 0.f;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     if (c >= nc) break;
-    const float4 w = w4[c], cc = col[c];
+    const float4 w = w4[c], cc = !PK || c >= cl ? col[c] : z4;
     q0 += w.x * w.x;
     q1 += w.y * w.y;
     q0 += w.z * w.z;
@@ -462,7 +508,7 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
     double w64 = 0.0;
     if (lane < t)
       for (int l = 0; l <= lane; ++l)
-        w64 += (double)LiR[lane * SP + l] * ((double)g1((int)supi[l], ia) * (double)g2(ja, (int)supj[l]));
+        w64 += (double)LiR[lrow<L>(lane) + l] * ((double)g1((int)supi[l], ia) * (double)g2(ja, (int)supj[l]));
     const double ww64 = wave_sum(lane < t ? w64 * w64 : 0.0);
     wave_sync();
     if (lane < t) xw[lane] = (float)w64;
@@ -472,7 +518,7 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (c >= nc) break;
-      const float4 w = w4[c], cc = col[c];
+      const float4 w = w4[c], cc = !PK || c >= cl ? col[c] : z4;
       v0 += cc.x * w.x;
       v1 += cc.y * w.y;
       v0 += cc.z * w.z;
@@ -487,14 +533,14 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
   cst_out = cst;
   const float dinv = 1.f / sqrtf(d2);
   if (lane < t) {
-    LiR[t * SP + lane] = -v * dinv;
-    LiT[lane * SP + t] = -v * dinv;
+    LiR[lrow<L>(t) + lane] = -v * dinv;
+    LiT[lcol<L>(lane) + t - lcol0<L>(lane)] = -v * dinv;
     my_x -= cst * v;
     gam[lane] = cst * v;
   }
   if (lane == t) {
-    LiR[t * SP + t] = dinv;
-    LiT[t * SP + t] = dinv;
+    LiR[lrow<L>(t) + t] = dinv;
+    LiT[lcol<L>(t) + t - lcol0<L>(t)] = dinv;
     my_x = cst;
     my_i = ia;
     my_j = ja;
@@ -537,9 +583,9 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
   }
   float* ysT = sW[wv];          // Y[p, q] at q + YQ p; columns m2 .. 16 TQ - 1 stay zero
   float* Ws = ysT + L::YT;      // W[i, q] at i + P1W q (first correlation only)
-  float* LiR = Ws;              // L^{-1}[k, l] at k SP + l (greedy loop; aliases W)
-  float* LiT = LiR + S * SP;    // L^{-1}[k, l] at l SP + k
-  float* gam = LiT + S * SP;    // refresh coefficients gamma_q (zero beyond the support)
+  float* LiR = Ws;              // L^{-1}[k, l] at lrow(k) + l (greedy loop; aliases W)
+  float* LiT = LiR + L::LPK;    // L^{-1}[k, l] at lcol(l) + k - 4 (l / 4)
+  float* gam = LiT + L::LPK;    // refresh coefficients gamma_q (zero beyond the support)
   float* supi = gam + SP;       // support atoms i_q, j_q (exact small integers)
   float* supj = supi + SP;
   float* xg = supj + SP;        // exchange vectors: Gram column g, then w
@@ -756,7 +802,15 @@ __global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<fl
     }
     wave_sync();
   }
-  if (lane == 0 && n_early) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)n_early);
+  // one atomic per workgroup: atomics on one address from every wave serialise
+  __shared__ unsigned sEarly[C::WPB];
+  if (lane == 0) sEarly[wv] = n_early;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned tot = 0;
+    for (int w = 0; w < C::WPB; ++w) tot += sEarly[w];
+    if (tot) atomicAdd(&a.counters[kCtrEarlyStop], (unsigned long long)tot);
+  }
 }
 
 // One signal per wave up to kWaveMaxBlocks workgroups (a persistent grid measured slower:

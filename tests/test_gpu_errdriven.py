@@ -36,10 +36,12 @@ def test_error_driven_matches_oracle(dtype, band, ctol, kernel):
     err2 = (1.15 * w.sigma() * np.sqrt(m)) ** 2
     so, co, ro = oracle.omp(Y, d1, d2, s, err2=err2, p=8)
     pr = api.Problem.from_math(Y, d1, d2, s, dtype=dtype, device=DEV)
-    api.sparse_code(pr, kernel=kernel, err2=err2)
+    st = api.new_stats()
+    api.sparse_code(pr, kernel=kernel, err2=err2, stats=st)
     torch.cuda.synchronize()
     sg, cg, rg = pr.supp.cpu().numpy(), pr.coef.cpu().double().numpy(), pr.res2.cpu().double().numpy()
     ng, no = np.sum(sg >= 0, axis=1), np.sum(so >= 0, axis=1)
+    assert st.early_stops == int(np.sum(ng < s))  # every signal that stopped below the cap, once
     assert len(set(no.tolist())) > 3 and np.mean(no < s) > 0.9  # the stop decides, rarely the cap
     same = ng == no
     for k in np.nonzero(~same)[0]:
