@@ -245,10 +245,9 @@ int sdl_image_to_patches(const void* image, int32_t H, int32_t W, int32_t m1, in
  * coef and N = (H-m1+1)(W-m2+1); Y and res2 unused): every pixel is the plain average, over the patches
  * covering it, of D1 X_k D2^T at that pixel (a reading: the paper does not say how overlapping
  * estimates are combined).  options->prec (SDL_FP32 or SDL_FP64) is the type of coef and image.
- * Unused support slots (-1) may sit anywhere in a code.  The call also needs N*m1*m2 elements of
- * scratch for the patches' estimates: with options->workspace that buffer must hold them beyond
- * what sdl_workspace_bytes reports for sparse coding (call 0) of p, rounded up to 256 bytes
- * (SDL_E_NOMEM otherwise).
+ * Unused support slots (-1) may sit anywhere in a code.  The estimates are formed on chip, pixel
+ * by pixel, and never stored: with options->workspace that buffer must hold what
+ * sdl_workspace_bytes reports for sparse coding (call 0) of p (SDL_E_NOMEM otherwise).
  * Asynchronous on `stream`. */
 int sdl_patches_to_image(const sdl_problem* p, int32_t H, int32_t W, const sdl_options* o, void* image,
                          void* stream);

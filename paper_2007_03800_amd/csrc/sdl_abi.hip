@@ -87,6 +87,7 @@ int get_ctx(hipStream_t st, Ctx** out) {
     if (e == hipSuccess) e = tmod_sums_bf16_init_device();
     if (e == hipSuccess) e = ortho_init_device();
     if (e == hipSuccess) e = tensor_init_device();
+    if (e == hipSuccess) e = denoise_init_device();
     if (e != hipSuccess) {
       delete c;
       return fail(SDL_E_DEVICE, "kernel attribute setup: %s", hipGetErrorString(e));
@@ -1304,17 +1305,14 @@ int patches_to_image_impl(const sdl_problem* p, int H, int W, const Opt& o, void
   SDL_TRY(get_ctx(st, &ctx));
   Plan pl;
   layout(p, 1, sizeof(T), 0, nullptr, &pl);
-  // the patches' estimates follow the call's usual workspace
-  const size_t est_off = (pl.bytes + 255) / 256 * 256;
-  const size_t bytes = est_off + sizeof(T) * (size_t)p->N * p->m1 * p->m2;
   void* wsb = nullptr;
-  SDL_TRY(acquire_ws(ctx, o, bytes, st, &wsb));
+  SDL_TRY(acquire_ws(ctx, o, pl.bytes, st, &wsb));
   layout(p, 1, sizeof(T), 0, wsb, &pl);
   std::vector<std::pair<int, int>> marks;
   Launcher L{st, false, ctx, &marks};
   SDL_TRY(run_prep<T>(p[0], pl.pb[0], L));
   HIP_TRY(launch_patches_to_image<T>(p->supp, (const T*)p->coef, (const T*)pl.pb[0].Dc1, (const T*)pl.pb[0].Dc2, H, W,
-                                     p->m1, p->m2, p->n1, p->n2, p->s, (T*)((char*)wsb + est_off), (T*)image, st));
+                                     p->m1, p->m2, p->n1, p->n2, p->s, (T*)image, st));
   return SDL_OK;
 }
 

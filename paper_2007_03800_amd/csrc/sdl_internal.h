@@ -256,9 +256,11 @@ hipError_t launch_kron_tail(const TensorArgs<double>& d, double* Dk, hipStream_t
 // signals, and the image rebuilt as the average of the coded patches covering each pixel.
 template <typename T>
 hipError_t launch_image_to_patches(const T* img, int H, int W, int m1, int m2, T* out, hipStream_t st);
-// blocks: (H - m1 + 1)(W - m2 + 1) m1 m2 elements of scratch (the patches' estimates)
+// (one pass, no scratch); denoise_init_device raises the rebuild kernel's LDS limit (call once
+// per device)
 template <typename T>
 hipError_t launch_patches_to_image(const int32_t* supp, const T* coef, const T* D1, const T* D2, int H, int W, int m1,
-                                   int m2, int n1, int n2, int s, T* blocks, T* img, hipStream_t st);
+                                   int m2, int n1, int n2, int s, T* img, hipStream_t st);
+hipError_t denoise_init_device();
 
 }  // namespace sdl

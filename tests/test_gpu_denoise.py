@@ -59,8 +59,13 @@ def _rebuild(d1t, d2t, supp, coef, H, W, dtype):
 
 @pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-12), (torch.float32, 1e-5)], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("H,W,m1,m2,n1,n2,s", [(40, 33, 8, 8, 16, 16, 6), (17, 23, 5, 7, 9, 11, 4),
-                                                (12, 12, 12, 12, 20, 20, 10)])
+                                                (12, 12, 12, 12, 20, 20, 10), (37, 20, 6, 6, 8, 8, 32),
+                                                (40, 36, 32, 24, 64, 48, 20), (70, 70, 64, 64, 40, 40, 8)])
 def test_patches_to_image_matches_oracle(H, W, m1, m2, n1, n2, s, dtype, bar, rng):
+    """Also the rebuild's on-chip limits: up to 4 used slots per patch are kept on chip, patches
+    with more are read from memory (20% unused slots at s = 6 and 10 mixes both, s = 32 has nearly
+    every patch beyond it); the large patches keep 2, 1 or no slots on chip (the last one, 64 x 40
+    FP64 dictionaries, needs more than 64 KiB of LDS)."""
     d1 = rng.standard_normal((m1, n1))
     d2 = rng.standard_normal((m2, n2))
     N = (H - m1 + 1) * (W - m2 + 1)
