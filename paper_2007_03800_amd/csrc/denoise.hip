@@ -14,15 +14,33 @@
 namespace sdl {
 namespace {
 
+// A wave copies kPatchU patches at a time (wave-uniform patch indices, grid-stride): lane e of
+// a chunk of kWave elements takes element e = i + m1 j of each, all loads issued before the
+// stores (one load-store chain per wave leaves the copy latency-bound), and each patch's m1 m2
+// values go out as one contiguous run.
+constexpr int kPatchU = 8;
+
 template <typename T>
-__global__ void image_to_patches_kernel(const T* __restrict__ img, int H, int W, int m1, int m2, T* __restrict__ out,
-                                        int64_t total) {
+__global__ void __launch_bounds__(256) image_to_patches_kernel(const T* __restrict__ img, int H, int W, int m1, int m2,
+                                                               T* __restrict__ out, int64_t N) {
   const int C = W - m2 + 1, M = m1 * m2;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = e / M;
-    const int px = (int)(e % M), i = px % m1, j = px / m1;
-    const int64_t r = k / C, c = k % C;
-    out[e] = img[(r + i) * W + (c + j)];
+  const int lane = threadIdx.x % kWave;
+  const int wpb = blockDim.x / kWave;
+  const int64_t w0 = (int64_t)blockIdx.x * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t nwv = (int64_t)gridDim.x * wpb;
+  for (int e0 = 0; e0 < M; e0 += kWave) {
+    const int e = e0 + lane, i = e % m1, j = e / m1;
+    for (int64_t k0 = w0 * kPatchU; k0 < N; k0 += nwv * kPatchU) {
+      T v[kPatchU];
+#pragma unroll
+      for (int u = 0; u < kPatchU; ++u) {
+        const int64_t k = k0 + u, r = k / C, c = k - r * C;
+        v[u] = e < M && k < N ? img[(r + i) * W + (c + j)] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kPatchU; ++u)
+        if (e < M && k0 + u < N) out[(k0 + u) * M + e] = v[u];
+    }
   }
 }
 
@@ -40,7 +58,7 @@ __global__ void image_to_patches_kernel(const T* __restrict__ img, int H, int W,
 // Estimates never reach HBM: the codes are read about ((kTile + m - 1) / kTile)^2 times (the
 // overlaps mostly from L2) and the image written once.
 constexpr int kTile = 16;
-constexpr int kStageU = 4;
+constexpr int kStageU = 8;
 constexpr size_t kRebuildLds = 40 * 1024;  // four workgroups per CU
 
 template <typename T>
@@ -55,9 +73,9 @@ __global__ void __launch_bounds__(kTile* kTile) rebuild_kernel(const int32_t* __
   T* sD2 = sD1 + m1 * n1;                                      // m2 x n2
   T* tcf = sD2 + m2 * n2;                                      // pool coefficients
   unsigned* tof = reinterpret_cast<unsigned*>(tcf + pool);     // pool offsets m1 i | (m2 j) << 16
-  int* nz = reinterpret_cast<int*>(tof + pool);                // used slots of each patch
-  int* pb = nz + PT;                                           // its pool start, -1: not in the pool
-  int* top = pb + PT;                                          // pool entries reserved
+  // per patch: its used slots and pool start (-1: not in the pool), 8-byte aligned
+  int2* nb = reinterpret_cast<int2*>(((uintptr_t)(tof + pool) + 7) & ~(uintptr_t)7);
+  int* top = reinterpret_cast<int*>(nb + PT);  // pool entries reserved
   const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, nw = blockDim.x / kWave;
   const int y0 = blockIdx.y * kTile, x0 = blockIdx.x * kTile;
   // the block's covering patches: rows rb..re and columns cb..ce of the patch grid
@@ -99,10 +117,7 @@ __global__ void __launch_bounds__(kTile* kTile) rebuild_kernel(const int32_t* __
       const bool fits = base + cnt <= pool;
       if (p < np) {
         const int lp = (p / npc) * PC + p % npc;
-        if (sl == 0) {
-          nz[lp] = cnt;
-          pb[lp] = fits ? base : -1;
-        }
+        if (sl == 0) nb[lp] = make_int2(cnt, fits ? base : -1);
         if (a[u] >= 0 && fits) {
           tof[base + pos] = (unsigned)(m1 * (a[u] % n1)) | ((unsigned)(m2 * (a[u] / n1)) << 16);
           tcf[base + pos] = cf[u];
@@ -118,7 +133,9 @@ __global__ void __launch_bounds__(kTile* kTile) rebuild_kernel(const int32_t* __
   T acc = 0;
   for (int r = r0; r <= r1; ++r)
     for (int c = c0; c <= c1; ++c) {
-      const int i = y - r, j = x - c, lp = (r - rb) * PC + (c - cb), n = nz[lp], b = pb[lp];
+      const int i = y - r, j = x - c;
+      const int2 cb2 = nb[(r - rb) * PC + (c - cb)];
+      const int n = cb2.x, b = cb2.y;
       T v = 0;
       if (b >= 0) {
         for (int q = b; q < b + n; ++q) {
@@ -143,19 +160,18 @@ template <typename T>
 size_t rebuild_lds_bytes(int m1, int m2, int n1, int n2, int pool) {
   const size_t pt = (size_t)(kTile + m1 - 1) * (kTile + m2 - 1);
   return sizeof(T) * ((size_t)m1 * n1 + (size_t)m2 * n2) + (sizeof(T) + sizeof(unsigned)) * (size_t)pool +
-         sizeof(int) * (2 * pt + 1);
+         8 + sizeof(int2) * pt + sizeof(int);  // 8: alignment of the int2 table
 }
 
 }  // namespace
 
 template <typename T>
 hipError_t launch_image_to_patches(const T* img, int H, int W, int m1, int m2, T* out, hipStream_t st) {
-  const int64_t total = (int64_t)(H - m1 + 1) * (W - m2 + 1) * m1 * m2;
-  if (total <= 0) return hipSuccess;
-  int64_t blocks = (total + 255) / 256;
+  const int64_t N = (int64_t)(H - m1 + 1) * (W - m2 + 1);
+  if (N <= 0) return hipSuccess;
+  int64_t blocks = (N + 4 * kPatchU - 1) / (4 * kPatchU);  // four waves per workgroup
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(image_to_patches_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, img, H, W, m1, m2, out,
-                     total);
+  hipLaunchKernelGGL(image_to_patches_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, img, H, W, m1, m2, out, N);
   return hipGetLastError();
 }
 
