@@ -204,8 +204,17 @@ __global__ void __launch_bounds__(kWave) procrustes_kernel(const double* __restr
   const int x = threadIdx.x;
   const int nent = n * n;
   for (int e = x; e < nent; e += kWave) {
+    // B follows A in the row; eight rows' loads in flight, added in row order
     double v = 0.0;
-    for (int b = 0; b < nrow; ++b) v += src[(size_t)b * ld + nent + e];  // B follows A in the row
+    int b = 0;
+    for (; b + 8 <= nrow; b += 8) {
+      double q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = src[(size_t)(b + u) * ld + nent + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += q[u];
+    }
+    for (; b < nrow; ++b) v += src[(size_t)b * ld + nent + e];
     W[e] = v;
     V[e] = (e % n) == (e / n) ? 1.0 : 0.0;
   }
