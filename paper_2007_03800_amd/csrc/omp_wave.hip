@@ -850,8 +850,10 @@ const WaveVariant kWaveVariants[] = {
 
 // FP32 one-wave shapes used only by the n-dimensional path, with every mode after the first
 // collapsed into one Kronecker factor D_n (x) ... (x) D_2 (so m2 and n2 are products and may
-// exceed the two-mode limits): (m1, m2, n1, n2, s, LR, LC, waves per workgroup)
-#define SDL_WAVE_COLLAPSED_SHAPES(X) X(8, 32, 12, 72, 8, 4, 8, 4)
+// exceed the two-mode limits): (m1, m2, n1, n2, s, LR, LC, waves per workgroup).  Eight waves
+// share the 34 KB of dictionary tables: 4 waves per SIMD (the register limit) instead of the
+// 3 that LDS allows with four.
+#define SDL_WAVE_COLLAPSED_SHAPES(X) X(8, 32, 12, 72, 8, 4, 8, 8)
 
 const WaveVariant kWaveCollapsed[] = {
 #define X(A_, B_, C_, D_, E_, F_, G_, H_) \
