@@ -343,7 +343,7 @@ def ortho_workload(api, oracle, synth):
             "rmse_vs_oracle": float(np.sqrt(r_g.mean()) / np.sqrt(r_o.mean())),
             **support_agreement(pr.supp[:nsub].cpu().numpy(), s_o),
             "code_kernel_ms": ms, "code_hbm_gbs": nbytes / (ms * 1e-3) / 1e9,
-            "code_kernel": "omp_mfma_kernel<MCfg<8, 8, 8, 8, 8, 2>, true> (first correlation on 4x4x1 MFMA, "
+            "code_kernel": "omp_mfma_kernel<MCfg<8, 8, 8, 8, 8, 3>, true> (first correlation on 4x4x1 MFMA, "
                            "exact top-s selection, Procrustes B sums in the epilogue)"}
 
 
