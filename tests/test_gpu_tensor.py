@@ -6,7 +6,8 @@ Bars as for two modes: FP64 supports identical except classified near-ties (1e-9
 1e-10 element-wise (relative to max(|x|, 0.02 max|x|)), dictionaries 1e-10 relative from identical
 codes and 1e-9 over a learning run; FP32 supports identical except near-ties at 1e-4, coefficients
 1e-4, dictionaries 1e-4 from identical codes.  Cases: two, three and four modes, non-square modes,
-a ragged signal count, the error-driven stop, an atom no code uses, an empty problem."""
+a ragged signal count, the error-driven stop, an atom no code uses, an empty problem, and the
+mode sums with every partial row filled (20,000 signals of the benchmarked shape)."""
 import numpy as np
 import pytest
 import torch
@@ -185,3 +186,25 @@ def test_tensor_workload_full_size_sampled():
     print("trace", trace, "sampled %d: agree %d, ties %d, bad %d, coef err %.2e" % (len(idx), agree, ties, bad, err))
     assert bad == 0 and err <= 1e-4
     assert trace[-1] < 0.5 * trace[0]
+
+
+def test_tensor_update_many_rows():
+    """The FP32 mode sums at a signal count that fills every partial row (20,000 signals of the
+    benchmarked 8 x 8 x 4 shape, 12 x 12 x 6 atoms, s = 8: 8,192 rows of about 2.4 signals each),
+    each mode's update from the GPU's own codes against the oracle's update from the same codes."""
+    w = synth.TENSOR_WORKLOADS["tensor_8x8x4_n12x12x6_s8"]
+    N = 20000
+    Y = synth.tensor_signals(w, 0, N).astype(np.float32).astype(np.float64)
+    E = synth.tensor_dictionaries(w, initial=True)
+    for mode in (1, 2, 3):
+        pr = api.TensorProblem.from_math(Y, E, w.s, dtype=torch.float32)
+        api.tensor_sparse_code(pr)
+        torch.cuda.synchronize()
+        sg, cg, _ = _codes(pr)
+        Dn, co, _ = ot.tensor_update(mode, Y, E, sg, cg)
+        api.tensor_update(pr, mode)
+        torch.cuda.synchronize()
+        errs = [np.abs(g - o).max() / np.abs(o).max() for g, o in zip(pr.dicts(), Dn)]
+        cerr = np.abs(pr.coef.cpu().double().numpy() - co).max() / np.abs(co).max()
+        print("mode", mode, "D errs", ["%.1e" % e for e in errs], "coef %.1e" % cerr)
+        assert max(errs) <= 1e-4 and cerr <= 1e-4
