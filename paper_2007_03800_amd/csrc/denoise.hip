@@ -7,8 +7,8 @@
 // Image: row-major, pixel (y, x) at y W + x.  Patch k = r C + c (C = W - m2 + 1) holds pixel
 // (r + i, c + j) at its (i, j), stored column-major like every signal of the library.
 // The rebuild is one tiled pass (rebuild_kernel): each output pixel sums its covering patches'
-// estimates in a fixed order, computed on the fly from codes gathered into LDS; there are no
-// atomics and the result is reproducible.
+// estimates in a fixed order, computed on the fly from codes gathered into LDS; nothing adds
+// into the image atomically and the result is reproducible.
 #include "sdl_internal.h"
 
 namespace sdl {
