@@ -417,6 +417,9 @@ struct MLay {
   static constexpr int WSM = P1W * C::M2;
   static constexpr int C4 = (C::S + 3) / 4;        // float4 chunks of a full row of L^{-1}
   static constexpr bool PK = C::S >= 24;             // packed copies of L^{-1}
+  // waves per SIMD the registers must allow: with packed copies LDS allows 6, and the
+  // compiler's own choice lands one register above that (12 bytes per lane spill instead)
+  static constexpr int MINW = PK ? 6 : 1;
   static constexpr int LPK = PK ? 8 * C4 * (C4 + 1) : C::S * SP;  // one copy (rows or columns)
   static constexpr int SCR = 2 * LPK + 5 * SP;       // L^{-1} by rows and by columns, gam, supi, supj, g, w
   static constexpr int UNI = ((WSM > SCR ? WSM : SCR) + 3) / 4 * 4;  // W staging aliases the scratch
@@ -469,13 +472,13 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
   const int cl = rw >> 2;  // packed: last chunk of row rw, first chunk of column rw
   const float4* row = reinterpret_cast<const float4*>(LiR + lrow<L>(rw));
   const float4* g4 = reinterpret_cast<const float4*>(xg);
-  const float4 z4 = {0.f, 0.f, 0.f, 0.f};
   float p0 = 0.f, p1 = 0.f;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     if (c >= nc) break;
-    // past its last chunk a row's storage holds the next rows: read in bounds, use zeros
-    const float4 r = !PK || c <= cl ? row[c] : z4, gg = g4[c];
+    // past its last chunk a row's storage holds the next rows: this lane stops there
+    if (PK && c > cl) break;
+    const float4 r = row[c], gg = g4[c];
     p0 += r.x * gg.x;
     p1 += r.y * gg.y;
     p0 += r.z * gg.z;
@@ -491,15 +494,18 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     if (c >= nc) break;
-    const float4 w = w4[c], cc = !PK || c >= cl ? col[c] : z4;
+    const float4 w = w4[c];
     q0 += w.x * w.x;
     q1 += w.y * w.y;
     q0 += w.z * w.z;
     q1 += w.w * w.w;
-    v0 += cc.x * w.x;
-    v1 += cc.y * w.y;
-    v0 += cc.z * w.z;
-    v1 += cc.w * w.w;
+    if (!PK || c >= cl) {  // before its first chunk a column's entries are zero
+      const float4 cc = col[c];
+      v0 += cc.x * w.x;
+      v1 += cc.y * w.y;
+      v0 += cc.z * w.z;
+      v1 += cc.w * w.w;
+    }
   }
   float v = v0 + v1;
   float d2 = gaa - (q0 + q1);
@@ -518,11 +524,13 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (c >= nc) break;
-      const float4 w = w4[c], cc = !PK || c >= cl ? col[c] : z4;
-      v0 += cc.x * w.x;
-      v1 += cc.y * w.y;
-      v0 += cc.z * w.z;
-      v1 += cc.w * w.w;
+      if (!PK || c >= cl) {
+        const float4 w = w4[c], cc = col[c];
+        v0 += cc.x * w.x;
+        v1 += cc.y * w.y;
+        v0 += cc.z * w.z;
+        v1 += cc.w * w.w;
+      }
     }
     v = v0 + v1;
     d2 = (float)((double)gaa - ww64);
@@ -553,7 +561,8 @@ __device__ inline bool append_atom_sq(int t, int lane, int ia, int ja, float bs,
 }
 
 template <class C>
-__global__ void __launch_bounds__(kWave* C::WPB) omp_wave_mfma_kernel(OmpArgs<float> a) {
+__global__ void __launch_bounds__(kWave* C::WPB) __attribute__((amdgpu_waves_per_eu(MLay<C>::MINW)))
+    omp_wave_mfma_kernel(OmpArgs<float> a) {
   using L = MLay<C>;
   constexpr int M1 = C::M1, M2 = C::M2, N1 = C::N1, N2 = C::N2, S = C::S, M = C::M, SP = C::SP;
   constexpr int TR = L::TR, TC = L::TC, TQ = L::TQ, P1 = L::P1, P2 = L::P2, YQ = L::YQ, P1W = L::P1W;
